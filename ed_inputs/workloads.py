@@ -1,0 +1,121 @@
+"""Named model configurations shaped like the paper's benchmark clusters.
+
+The paper benchmarks the nearest-neighbour Heisenberg antiferromagnet on
+triangular, square and kagome clusters with translations, a (sublattice
+stable) point group and spin flip, each with a multi-sublattice decomposition
+(sec. "Benchmarks", Table of benchmarks, Fig. of benchmark geometries).  Those
+48/50-site sectors do not fit one GPU, so the workloads here are the same
+families at 16-40 sites.  Each workload returns the cluster (with its
+sublattice renumbering), the irrep characters, n_up and the couplings.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import lattice as lat
+from .vectors import couplings_by_kind, random_couplings
+
+
+@dataclass
+class Workload:
+    name: str
+    cluster: lat.Cluster
+    chi: np.ndarray          # complex128 [n_elems]
+    n_up: int
+    J: np.ndarray            # float64 [n_bonds]
+    description: str = ""
+
+    @property
+    def is_complex(self):
+        return bool(np.any(np.abs(self.chi.imag) > 1e-14))
+
+
+# sublattice superlattices (generators in lattice coordinates)
+SQ_CHECKER = ((1, 1), (1, -1))        # 2 sublattices
+SQ_2X2 = ((2, 0), (0, 2))             # 4 sublattices
+SQ_5 = ((1, 2), (-2, 1))              # 5 sublattices, label (x + 2y) mod 5
+SQ_8 = ((2, 2), (-2, 2))              # 8 sublattices
+SQ_10 = ((3, 1), (-1, 3))             # 10 sublattices
+TRI_3 = ((1, 1), (3, 0))              # 3 sublattices, label (a - b) mod 3
+TRI_4 = ((2, 0), (0, 2))              # 4 sublattices
+TRI_9 = ((3, 0), (0, 3))              # 9 sublattices
+
+
+def _trivial(cl):
+    return lat.characters(cl, 0)
+
+
+def square_4x4(n_sub=4, group="translations", momentum_index=0):
+    """4x4 periodic square, J=1, Sz=0; translation group, k=(0,0) by default."""
+    sup = {1: None, 2: SQ_CHECKER, 4: SQ_2X2}[n_sub]
+    if group == "translations":
+        cl = lat.square((4, 0), (0, 4), rotations=False, superlattice=sup, name="square16")
+    elif group == "full":
+        cl = lat.square((4, 0), (0, 4), rotations=True, mirrors=True, spin_flip=True,
+                        superlattice=sup, name="square16full")
+    else:
+        raise ValueError(group)
+    chi = lat.characters(cl, momentum_index)
+    return Workload("square16", cl, chi, 8, np.ones(cl.n_bonds),
+                    "Heisenberg J=1, 4x4 periodic square, Sz=0, translations, k=(0,0)")
+
+
+def triangular_36(n_sub=4):
+    """36-site triangular, full space group (36 T x C6v) x spin flip, Gamma.A1.even."""
+    sup = {3: TRI_3, 4: TRI_4, 9: TRI_9}[n_sub]
+    cl = lat.triangular((6, 0), (0, 6), spin_flip=True, superlattice=sup, name="triangular36")
+    return Workload("triangular36", cl, _trivial(cl), 18, np.ones(cl.n_bonds),
+                    "Heisenberg J=1, 36-site triangular, Sz=0, 36 T x C6v x flip, Gamma.A1.even")
+
+
+def square_40_j1j2(n_sub=5, j2=0.5):
+    """40-site tilted square (L1=(6,2), L2=(-2,6)), J1-J2, 40 T x C4 x flip, Gamma."""
+    sup = {2: SQ_CHECKER, 4: SQ_2X2, 5: SQ_5, 8: SQ_8, 10: SQ_10}[n_sub]
+    cl = lat.square((6, 2), (-2, 6), j2=True, spin_flip=True, superlattice=sup, name="square40")
+    J = couplings_by_kind(cl.bond_kind, [1.0, j2])
+    return Workload("square40_j1j2", cl, _trivial(cl), 20, J,
+                    f"J1-J2 (J2/J1={j2}), 40-site tilted square, Sz=0, 40 T x C4 x flip, Gamma.A.even")
+
+
+def triangular_36_momentum(momentum_index, n_sub=4):
+    """36-site triangular, translations only, momentum sector k (complex if k != -k)."""
+    sup = {3: TRI_3, 4: TRI_4, 9: TRI_9}[n_sub]
+    cl = lat.triangular((6, 0), (0, 6), rotations=False, mirrors=False, superlattice=sup,
+                        name="triangular36T")
+    return Workload(f"triangular36_k{momentum_index}", cl, lat.characters(cl, momentum_index), 18,
+                    np.ones(cl.n_bonds), "Heisenberg J=1, 36-site triangular, translations, one momentum")
+
+
+def square_32_disorder(n_sub=8, seed=1):
+    """32-site tilted square (L1=(4,4), L2=(-4,4)), translations, k=0, J_b ~ U(0.8,1.2)."""
+    sup = {2: SQ_CHECKER, 4: SQ_2X2, 8: SQ_8}[n_sub]
+    cl = lat.square((4, 4), (-4, 4), rotations=False, superlattice=sup, name="square32")
+    return Workload("square32_disorder", cl, _trivial(cl), 16, random_couplings(cl.n_bonds, seed),
+                    "Heisenberg, 32-site tilted square, Sz=0, translations, k=0, J_b~U(0.8,1.2)")
+
+
+def square_20_j1j2(n_sub=5, j2=0.5, spin_flip=True):
+    """20-site tilted square (L1=(4,2), L2=(-2,4)), J1-J2, T x C4 (x flip); small C3 analogue."""
+    sup = {1: None, 2: SQ_CHECKER, 4: SQ_2X2, 5: ((2, 1), (-1, 2)), 10: ((1, 3), (-3, 1))}[n_sub]
+    cl = lat.square((4, 2), (-2, 4), j2=True, spin_flip=spin_flip, superlattice=sup, name="square20")
+    J = couplings_by_kind(cl.bond_kind, [1.0, j2])
+    return Workload("square20_j1j2", cl, _trivial(cl), 10, J, "J1-J2, 20-site tilted square")
+
+
+def triangular_12(n_sub=3, spin_flip=True, momentum_index=0, rotations=True, mirrors=True):
+    """12-site triangular (L1=(4,-2)... via (2,2),(-2,4)), small C2 analogue."""
+    sup = {1: None, 3: TRI_3}[n_sub]
+    cl = lat.triangular((2, 2), (-2, 4), rotations=rotations, mirrors=mirrors, spin_flip=spin_flip,
+                        superlattice=sup, name="triangular12")
+    return Workload("triangular12", cl, lat.characters(cl, momentum_index), 6, np.ones(cl.n_bonds),
+                    "Heisenberg, 12-site triangular")
+
+
+WORKLOADS = {
+    "square16": square_4x4,
+    "triangular36": triangular_36,
+    "square40_j1j2": square_40_j1j2,
+    "square32_disorder": square_32_disorder,
+}
