@@ -1,0 +1,240 @@
+/*
+ * ed.h -- C ABI of the MI355X (gfx950) symmetry-sector exact-diagonalisation
+ * hot path: sublattice-coding representative search, index lookup in the
+ * sorted basis, and the bond-loop Heisenberg H.v, plus Lanczos and the
+ * adjoint.  Method: A. Wietek and A. M. Laeuchli, "Sublattice coding
+ * algorithm and distributed memory parallelization for large-scale exact
+ * diagonalizations of quantum many-body systems" (arXiv:1804.05028).
+ *
+ * General rules
+ *  - Every call returns an int status: ED_OK (0) or a negative ED_ERR_* code.
+ *    Nothing throws across this boundary.  ed_last_error() returns a
+ *    thread-local message describing the last failure on the calling thread.
+ *  - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *    device memory on the current device (for example PyTorch tensors'
+ *    data_ptr()).  The caller owns every pointer it passes; the library owns
+ *    the opaque handles it returns and every device buffer inside them.
+ *  - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls that only enqueue work return once it is enqueued; calls that
+ *    return host results synchronise the stream first.
+ *  - Spin configurations are uint64 codes: site s <-> bit (N-1-s), so site 0
+ *    is the most significant bit, and up = 1 (sec. "Symmetry adapted basis
+ *    states"; the worked examples' integers (011)_2 = 3 fix this order).
+ *  - Vectors are FP64 (double) in ascending-representative order, or
+ *    complex128 stored as interleaved (re, im) doubles when the irrep has a
+ *    complex character (ed_basis_is_complex).
+ */
+#ifndef ED_MI355X_H
+#define ED_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define ED_OK 0
+#define ED_ERR_ARG (-1)                    /* null pointer, bad size, x == y, ...   */
+#define ED_ERR_NOT_GROUP (-2)              /* permutations not closed / no identity */
+#define ED_ERR_BAD_IRREP (-3)              /* chi not a homomorphism or |chi| != 1   */
+#define ED_ERR_NOT_SUBLATTICE_STABLE (-4)  /* some g splits a sublattice            */
+#define ED_ERR_FLIP_NEEDS_SZ0 (-5)         /* spin flip in the group but 2 n_up != N */
+#define ED_ERR_NONINVARIANT_H (-6)         /* bonds or couplings not group invariant */
+#define ED_ERR_OOM (-7)                    /* device allocation failed              */
+#define ED_ERR_HIP (-8)                    /* a HIP runtime call failed             */
+#define ED_ERR_UNSUPPORTED (-9)            /* size outside what this build handles  */
+
+/*
+ * Lattice: N sites, bonds, and the sublattice decomposition.
+ * Sublattice stability (sec. "Generic sublattice coding algorithm",
+ * Definition of sublattice stability): the sites must be numbered so that
+ * sublattice X is the block [X*N/n_sublat, (X+1)*N/n_sublat), which puts
+ * sublattice 0 on the most significant bits; every group element must map
+ * each block onto one block.  1 <= N <= 56 and N/n_sublat <= 16.
+ * bonds[2b], bonds[2b+1]: the two sites of bond b (distinct).  The
+ * Hamiltonian is H = sum_b J_b S_p.S_q (Eq. of the benchmark model,
+ * sec. "Benchmarks", with one coupling per bond).
+ */
+typedef struct {
+    int32_t n_sites;
+    int32_t n_bonds;
+    const int32_t *bonds;   /* host, [n_bonds][2] */
+    int32_t n_sublat;
+} ed_lattice_t;
+
+/*
+ * Group: n_elems site permutations, optionally combined with global spin
+ * flip.  perm[g*N + i] is the site to which element g moves the spin of site
+ * i; flip[g] = 1 also inverts every spin.  Must contain the identity and be
+ * closed under composition (g h)(i) = g(h(i)), flips adding mod 2.
+ * n_elems <= 65535.
+ */
+typedef struct {
+    int32_t n_elems;
+    const int32_t *perm;    /* host, [n_elems][N] */
+    const uint8_t *flip;    /* host, [n_elems]    */
+} ed_group_t;
+
+/*
+ * 1-D irrep: chi[2g], chi[2g+1] = (re, im) of chi(g), |chi| = 1,
+ * chi(g h) = chi(g) chi(h).  The sector holds the states with
+ * g|psi> = chi(g)|psi> (the span of the symmetry-adapted states of
+ * sec. "Symmetry adapted basis states").
+ */
+typedef struct {
+    const double *chi;      /* host, [n_elems][2] */
+} ed_irrep_t;
+
+/* Optional tuning; zero fields mean "choose automatically". */
+typedef struct {
+    int32_t limits_bits;    /* bits of the state after the top block used in the Limits key */
+    int32_t table_lds;      /* 1 = stage the symmetry-action table in LDS, 2 = read it from global, 0 = auto */
+    int32_t block_threads;  /* threads per block of the H.v kernel (64..1024, multiple of 64) */
+    int32_t blocks_per_cu;  /* persistent blocks per compute unit of the H.v kernel          */
+} ed_tuning_t;
+
+typedef struct ed_tables ed_tables_t;   /* host-side sublattice-coding tables */
+typedef struct ed_basis ed_basis_t;     /* device-resident sector basis       */
+
+typedef struct {
+    int32_t n_sites, n_sublat, sub_bits, n_elems, n_perms;
+    int64_t rep_entries;        /* n_sublat * 2^sub_bits                       */
+    int64_t sym_entries;        /* total length of all Sym_X lists             */
+    int64_t action_bytes;       /* bytes of the symmetry-action table          */
+    int32_t max_sym_len;        /* longest Sym_X list                          */
+    int32_t n_top;              /* distinct values a top block can take        */
+} ed_tables_info_t;
+
+typedef struct {
+    int64_t dim;                /* sector dimension D                          */
+    int32_t is_complex;
+    int32_t n_sites, n_up, n_sublat, sub_bits, n_elems, n_bonds;
+    int32_t limits_bits;        /* key bits after the top block                */
+    int64_t n_keys;             /* Limits entries - 1                          */
+    int32_t table_lds;          /* 1 if the action table is staged in LDS      */
+    int32_t lds_bytes;          /* LDS bytes per block of the H.v kernel       */
+    int64_t device_bytes;       /* device memory owned by the handle           */
+    double build_ms;            /* wall time of ed_build_basis                 */
+} ed_basis_info_t;
+
+/* Library version string (static). */
+const char *ed_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *ed_last_error(void);
+
+/*
+ * Check a model without touching the GPU: group closure and identity,
+ * character homomorphism and modulus, sublattice stability, spin flip only at
+ * 2 n_up = N, and group invariance of the bond set.  irrep may be NULL
+ * (skips the character checks), n_up < 0 skips the flip check.
+ */
+int ed_validate(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irrep_t *irrep, int32_t n_up);
+
+/*
+ * Sublattice-coding lookup tables on the host (Alg. "Preparation of lookup
+ * tables"; definitions of sublattice symmetries G_X, Rep_X, Sym_X and
+ * SymmetryAction_X in sec. "Generic sublattice coding algorithm").  Host
+ * only; used to inspect and test the tables the kernels use.
+ */
+int ed_tables_create(const ed_lattice_t *lat, const ed_group_t *grp, ed_tables_t **out);
+void ed_tables_free(ed_tables_t *t);
+int ed_tables_info(const ed_tables_t *t, ed_tables_info_t *info);
+
+/*
+ * Rep_X and Sym_X of one substate: *rep_out = Rep_X(substate) (an m-bit
+ * pattern placed on sublattice 0), sym_out[0..*n_sym) = the group indices of
+ * Sym_X(substate) in ascending order (at most cap are written; *n_sym is the
+ * full length).
+ */
+int ed_tables_sublattice(const ed_tables_t *t, int32_t X, uint32_t substate, uint32_t *rep_out,
+                         int32_t *sym_out, int32_t cap, int32_t *n_sym);
+
+/*
+ * Alg. "Sublattice coding algorithm for finding the representative", on the
+ * host, from the same tables: for each state, the representative (orbit
+ * minimum), one minimising group element, and the number of candidate
+ * symmetries examined.  Any of rep_out, g_out, n_cand_out may be NULL.
+ */
+int ed_tables_find_rep(const ed_tables_t *t, int64_t n, const uint64_t *states, uint64_t *rep_out,
+                       int32_t *g_out, int32_t *n_cand_out);
+
+/*
+ * Build the sector basis on the device (Alg. "Preparation of the distributed
+ * and symmetrized Hilbert space" on one device): every representative with
+ * n_up up spins whose stabiliser carries the trivial character, in ascending
+ * order, with its stabiliser size, and the Limits index over key prefixes.
+ * Validates as ed_validate does.  tuning may be NULL.  Synchronises stream.
+ */
+int ed_build_basis(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irrep_t *irrep,
+                   int32_t n_up, const ed_tuning_t *tuning, void *stream, ed_basis_t **out);
+void ed_free_basis(ed_basis_t *b);
+int64_t ed_basis_dim(const ed_basis_t *b);
+int ed_basis_is_complex(const ed_basis_t *b);
+int ed_basis_info(const ed_basis_t *b, ed_basis_info_t *info);
+
+/* Representatives in ascending order -> host [dim] (synchronises). */
+int ed_basis_copy_states(const ed_basis_t *b, uint64_t *host_out, void *stream);
+/* Representatives -> device [dim] (stream-ordered). */
+int ed_basis_copy_states_device(const ed_basis_t *b, uint64_t *dev_out, void *stream);
+/* |Stab sigma| of every representative -> host [dim] (synchronises). */
+int ed_basis_copy_norms(const ed_basis_t *b, uint16_t *host_out, void *stream);
+
+/*
+ * y = H x in the sector (Alg. "Parallel matrix-vector multiply" for the sum
+ * of all bond terms, in gather form): for row i with representative sigma_i,
+ * y_i = d_i x_i + sum over antiparallel bonds b of
+ *       (J_b / 2) * chi(g) * sqrt(n_j / n_i) * x_j,
+ * where sigma' = sigma_i with bond b flipped, g maps sigma' to its
+ * representative sigma_j = g sigma' (Eq. for matrix elements between
+ * representatives, conjugated for the row form), n = |Stab|, and
+ * d_i = sum_b J_b (+1/4 parallel, -1/4 antiparallel).  Terms whose target is
+ * not in the sector are dropped.  J: host [n_bonds], constant on bond orbits
+ * (else ED_ERR_NONINVARIANT_H).  x, y: device [dim] (complex: [dim][2]),
+ * distinct.  Enqueued on stream.
+ */
+int ed_apply_H(const ed_basis_t *b, const double *J, const void *x_dev, void *y_dev, void *stream);
+
+/*
+ * Term counts of one H.v: diagonal terms (= dim), off-diagonal terms whose
+ * target is in the sector, and dropped ones.  Synchronises.
+ */
+int ed_apply_H_stats(const ed_basis_t *b, int64_t *n_diag, int64_t *n_offdiag_kept,
+                     int64_t *n_offdiag_dropped, void *stream);
+
+/*
+ * Lanczos on the sector (the iteration whose cost the paper attributes to the
+ * matrix-vector product, sec. "Distributed and hybrid memory
+ * parallelization"): v_0 = v0 / |v0|; w = H v_j - beta_{j-1} v_{j-1};
+ * alpha_j = Re <v_j, w>; w -= alpha_j v_j; beta_j = |w|; v_{j+1} = w / beta_j.
+ * FP64 throughout, no reorthogonalisation.  Stops after n_steps or when
+ * beta_j <= 1e-12 * max_k(|alpha_k|, beta_k) (*n_done < n_steps).
+ * alpha_host, beta_host: host [n_steps].  If psi0_dev is not NULL a second,
+ * bit-identical pass writes the normalised lowest Ritz vector there.
+ * Synchronises.
+ */
+int ed_lanczos(const ed_basis_t *b, const double *J, const void *v0_dev, int32_t n_steps,
+               double *alpha_host, double *beta_host, int32_t *n_done, void *psi0_dev,
+               void *stream);
+
+/*
+ * Adjoint of y = H(J) x: gx = H^dagger gy (= H gy, H is Hermitian) if gx_dev
+ * is not NULL, and gJ_b = Re( gy^dagger dH/dJ_b x ) for every bond if gJ_host
+ * is not NULL, where dH/dJ_b collects bond b's diagonal and off-diagonal
+ * terms in the row form of ed_apply_H.  Synchronises if gJ_host is given.
+ */
+int ed_apply_H_backward(const ed_basis_t *b, const double *J, const void *x_dev, const void *gy_dev,
+                        void *gx_dev, double *gJ_host, void *stream);
+
+/*
+ * Eigenvalues (ascending) of the symmetric tridiagonal matrix with diagonal
+ * alpha[0..m) and off-diagonal beta[0..m-1), and optionally the eigenvector
+ * of the lowest one (evec0 [m], may be NULL).  Host only.
+ */
+int ed_tridiag_eigh(int32_t m, const double *alpha, const double *beta, double *evals, double *evec0);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

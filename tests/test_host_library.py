@@ -1,0 +1,222 @@
+"""Host-side checks of libed.so that need no GPU.
+
+The library loads, exports every function declared in include/ed.h, rejects
+invalid models with the documented status codes, and its sublattice-coding
+tables reproduce the paper's worked examples and the oracle's brute-force
+representatives.  No compute call touches a GPU here.
+"""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from ed_inputs import lattice as lat
+from ed_inputs import workloads as wl
+from oracle import bruteforce as bf
+from paper_1804_05028_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "ed.h")).read()
+    declared = set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]*?\b(ed_\w+)\s*\(", header, re.M))
+    assert {"ed_build_basis", "ed_apply_H", "ed_lanczos", "ed_apply_H_backward"} <= declared
+    lib = L.lib()
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(L.exported_symbols())
+    assert "gfx950" in L.ed_version()
+
+
+def _arrays(cl, chi=None):
+    return L.ModelArrays(cl.n_sites, cl.bonds, cl.n_sublat, cl.perm, cl.flip, chi)
+
+
+def test_validate_accepts_paper_shaped_models():
+    for w in (wl.square_4x4(), wl.triangular_36(), wl.square_40_j1j2(), wl.square_32_disorder(n_sub=8),
+              wl.triangular_12()):
+        L.ed_validate(_arrays(w.cluster, w.chi), w.n_up)
+
+
+def _expect(code, fn):
+    with pytest.raises(L.EDError) as ei:
+        fn()
+    assert ei.value.name == code, str(ei.value)
+
+
+def test_validate_rejects_bad_models():
+    w = wl.square_4x4()
+    c = w.cluster
+    # not closed: drop one translation
+    _expect("ED_ERR_NOT_GROUP",
+            lambda: L.ed_validate(L.ModelArrays(16, c.bonds, 4, c.perm[:-1], c.flip[:-1], w.chi[:-1]), 8))
+    # identity missing
+    _expect("ED_ERR_NOT_GROUP",
+            lambda: L.ed_validate(L.ModelArrays(16, c.bonds, 4, c.perm[1:2], c.flip[1:2], w.chi[1:2]), 8))
+    # character not a homomorphism
+    chi = w.chi.copy()
+    chi[3] = -1
+    _expect("ED_ERR_BAD_IRREP", lambda: L.ed_validate(_arrays(c, chi), 8))
+    chi = w.chi.copy() * 1.1
+    _expect("ED_ERR_BAD_IRREP", lambda: L.ed_validate(_arrays(c, chi), 8))
+    # 3 sublattices do not divide 16 sites
+    _expect("ED_ERR_NOT_SUBLATTICE_STABLE",
+            lambda: L.ed_validate(L.ModelArrays(16, c.bonds, 3, c.perm, c.flip, w.chi), 8))
+    # 4x4 square with the 90-degree rotation and the index-4 superlattice
+    # spanned by (2,0) and (1,2), which the rotation does not map onto itself
+    sq = lat.square((4, 0), (0, 4), rotations=True, superlattice=((2, 0), (1, 2)))
+    _expect("ED_ERR_NOT_SUBLATTICE_STABLE",
+            lambda: L.ed_validate(_arrays(sq, lat.characters(sq, 0)), 8))
+    # flip at Sz != 0
+    t = wl.triangular_12()
+    _expect("ED_ERR_FLIP_NEEDS_SZ0", lambda: L.ed_validate(_arrays(t.cluster, t.chi), 5))
+    # bonds not invariant: drop one bond
+    _expect("ED_ERR_NONINVARIANT_H",
+            lambda: L.ed_validate(L.ModelArrays(16, c.bonds[1:], 4, c.perm, c.flip, w.chi), 8))
+    # too many sites
+    _expect("ED_ERR_UNSUPPORTED",
+            lambda: L.ed_validate(L.ModelArrays(60, [[0, 1]], 1, np.arange(60)[None], [0], [1.0]), 30))
+
+
+# ---------------------------------------------------------------- worked examples
+
+def _gold():
+    with open(os.path.join(ROOT, "tests", "golden", "worked_examples.json")) as f:
+        return json.load(f)
+
+
+def _spins(s):
+    v = 0
+    for ch in s.replace(" ", ""):
+        v = 2 * v + (ch == "u")
+    return v
+
+
+def test_tables_two_sublattice_example():
+    ex = _gold()["two_sublattice"]
+    c = lat.chain(6, superlattice_period=2)
+    h = L.ed_tables_create(_arrays(c))
+    try:
+        s = ex["state_int"]
+        sA, sB = s >> 3, s & 7
+        repA, symA = L.ed_tables_sublattice(h, 0, sA)
+        repB, symB = L.ed_tables_sublattice(h, 1, sB)
+        assert repA == ex["rep_A"]["int"] and repB == ex["rep_B"]["int"]
+        assert symB == ex["sym_B"]
+        r, g, nc = L.ed_tables_find_rep(h, [s])
+        assert int(r[0]) == ex["representative"]["int"] and int(g[0]) == ex["representative"]["g"]
+        assert nc[0] == 1      # only Sym_B is examined, as Rep_B < Rep_A
+    finally:
+        L.ed_tables_free(h)
+
+
+def test_tables_three_sublattice_example():
+    ex = _gold()["three_sublattice"]
+    c = lat.chain(6, superlattice_period=3)
+    h = L.ed_tables_create(_arrays(c))
+    try:
+        s = ex["state_int"]
+        subs = [(s >> 4) & 3, (s >> 2) & 3, s & 3]
+        for X, key in enumerate("ABC"):
+            rep, sym = L.ed_tables_sublattice(h, X, subs[X])
+            assert rep == ex[f"rep_{key}"]["int"]
+            assert sym == ex[f"sym_{key}"]
+        r, g, nc = L.ed_tables_find_rep(h, [s])
+        assert int(r[0]) == ex["representative"]["int"] and int(g[0]) == ex["representative"]["g"]
+        assert nc[0] == 2      # T2 and T5, the symmetries of the minimal block B
+    finally:
+        L.ed_tables_free(h)
+
+
+# ---------------------------------------------------------------- Alg. 2 vs brute force
+
+def _all_states(n, k):
+    from itertools import combinations
+    out = []
+    for ups in combinations(range(n), k):
+        v = 0
+        for s in ups:
+            v |= 1 << (n - 1 - s)
+        out.append(v)
+    return np.array(out, np.uint64)
+
+
+@pytest.mark.parametrize("name", ["sq16_t4", "sq16_full2", "tri12_3", "sq20_5", "sq20_10", "chain12_flip_refl"])
+def test_host_find_rep_matches_bruteforce_exhaustive(name):
+    if name == "sq16_t4":
+        w = wl.square_4x4(n_sub=4)
+    elif name == "sq16_full2":
+        w = wl.square_4x4(n_sub=2, group="full")
+    elif name == "tri12_3":
+        w = wl.triangular_12()
+    elif name == "sq20_5":
+        w = wl.square_20_j1j2(n_sub=5)
+    elif name == "sq20_10":
+        w = wl.square_20_j1j2(n_sub=10)
+    else:
+        c = lat.chain(12, superlattice_period=2, reflection=True, spin_flip=True)
+        w = wl.Workload("chain12", c, lat.characters(c, 0), 6, np.ones(12))
+    c = w.cluster
+    states = _all_states(c.n_sites, w.n_up)
+    h = L.ed_tables_create(_arrays(c))
+    try:
+        r, g, _ = L.ed_tables_find_rep(h, states)
+    finally:
+        L.ed_tables_free(h)
+    m = bf.Model(c.n_sites, c.perm, c.flip, w.chi)
+    rb, _, _, _ = bf.rep_many(m, states)
+    assert np.array_equal(r, rb)
+    # the returned element really maps the state onto its representative
+    for k in range(0, len(states), max(1, len(states) // 500)):
+        assert bf.act(m, int(g[k]), int(states[k])) == int(r[k])
+
+
+@pytest.mark.parametrize("n_sub", [4, 9])
+def test_host_find_rep_random_triangular36(n_sub):
+    w = wl.triangular_36(n_sub=n_sub)
+    c = w.cluster
+    rng = np.random.default_rng(11)
+    keys = rng.random((20000, 36)).argsort(axis=1)[:, :18]
+    s = np.zeros(20000, np.uint64)
+    for k in range(18):
+        s |= np.left_shift(np.uint64(1), (35 - keys[:, k]).astype(np.uint64))
+    h = L.ed_tables_create(_arrays(c))
+    try:
+        r, _, _ = L.ed_tables_find_rep(h, s)
+    finally:
+        L.ed_tables_free(h)
+    rb, _, _, _ = bf.rep_many(bf.Model(36, c.perm, c.flip, w.chi), s)
+    assert np.array_equal(r, rb)
+
+
+@pytest.mark.parametrize("n_sub", [5, 8, 10])
+def test_host_find_rep_random_square40(n_sub):
+    w = wl.square_40_j1j2(n_sub=n_sub)
+    c = w.cluster
+    rng = np.random.default_rng(12)
+    keys = rng.random((20000, 40)).argsort(axis=1)[:, :20]
+    s = np.zeros(20000, np.uint64)
+    for k in range(20):
+        s |= np.left_shift(np.uint64(1), (39 - keys[:, k]).astype(np.uint64))
+    h = L.ed_tables_create(_arrays(c))
+    try:
+        r, _, _ = L.ed_tables_find_rep(h, s)
+    finally:
+        L.ed_tables_free(h)
+    rb, _, _, _ = bf.rep_many(bf.Model(40, c.perm, c.flip, w.chi), s)
+    assert np.array_equal(r, rb)
+
+
+def test_tridiag_eigh_matches_numpy():
+    rng = np.random.default_rng(3)
+    for m in (1, 2, 5, 60, 200):
+        a = rng.standard_normal(m)
+        b = np.abs(rng.standard_normal(max(m - 1, 0))) + 0.1
+        ev, vec = L.ed_tridiag_eigh(a, b)
+        T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+        w, V = np.linalg.eigh(T)
+        assert np.abs(ev - w).max() < 1e-12 * max(1, np.abs(w).max())
+        assert abs(abs(vec @ V[:, 0]) - 1) < 1e-10
