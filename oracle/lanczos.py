@@ -7,15 +7,16 @@ The paper runs Lanczos with its matrix-vector product as the dominant cost
 details.  The reading used here: start from the given vector normalised;
 w = H v_j - beta_{j-1} v_{j-1}; alpha_j = Re<v_j, w>; w -= alpha_j v_j;
 beta_j = ||w||; stop after n_steps or when beta_j <= 1e-12 * max_k(|alpha_k|,
-beta_k); no reorthogonalisation.  Eigenvalues of the tridiagonal T come from
-SciPy's ``eigh_tridiagonal``.
+beta_k); no reorthogonalisation.  Eigenpairs of the tridiagonal T come from
+a dense symmetric eigensolver (numpy.linalg.eigh on T), which stays robust
+when many Ritz values nearly coincide (ghost copies after loss of
+orthogonality), where LAPACK's MRRR tridiagonal driver can fail.
 
 Pins: closed-form ground energies and the dense spectrum at small N.
 """
 from __future__ import annotations
 
 import numpy as np
-from scipy.linalg import eigh_tridiagonal
 
 BREAKDOWN_TOL = 1e-12
 
@@ -48,13 +49,19 @@ def lanczos(matvec, v0, n_steps, want_vectors=False):
     return out
 
 
-def tridiag_eigenvalues(alpha, beta):
+def _tmatrix(alpha, beta):
     m = len(alpha)
-    if m == 0:
+    T = np.diag(np.asarray(alpha, dtype=np.float64))
+    if m > 1:
+        b = np.asarray(beta[: m - 1], dtype=np.float64)
+        T += np.diag(b, 1) + np.diag(b, -1)
+    return T
+
+
+def tridiag_eigenvalues(alpha, beta):
+    if len(alpha) == 0:
         return np.array([])
-    if m == 1:
-        return np.array([alpha[0]])
-    return eigh_tridiagonal(alpha, beta[: m - 1], eigvals_only=True)
+    return np.linalg.eigvalsh(_tmatrix(alpha, beta))
 
 
 def ground_state(matvec, v0, n_steps):
@@ -63,7 +70,7 @@ def ground_state(matvec, v0, n_steps):
     m = res["n_done"]
     if m == 1:
         return res["alpha"][0], res["vectors"][0]
-    w, s = eigh_tridiagonal(res["alpha"], res["beta"][: m - 1])
+    w, s = np.linalg.eigh(_tmatrix(res["alpha"], res["beta"]))
     psi = sum(s[k, 0] * res["vectors"][k] for k in range(m))
     return w[0], psi / np.linalg.norm(psi)
 
@@ -73,6 +80,6 @@ def converged_ritz(alpha, beta, resid_tol=1e-8):
     m = len(alpha)
     if m == 1:
         return np.array([alpha[0]])
-    w, s = eigh_tridiagonal(alpha, beta[: m - 1])
+    w, s = np.linalg.eigh(_tmatrix(alpha, beta))
     res = abs(beta[m - 1]) * np.abs(s[m - 1, :])
     return w[res < resid_tol]
