@@ -88,10 +88,15 @@ typedef struct {
 
 /* Optional tuning; zero fields mean "choose automatically". */
 typedef struct {
-    int32_t limits_bits;    /* bits of the state after the top block used in the Limits key */
-    int32_t table_lds;      /* 1 = stage the symmetry-action table in LDS, 2 = read it from global, 0 = auto */
-    int32_t block_threads;  /* threads per block of the H.v kernel (64..1024, multiple of 64) */
-    int32_t blocks_per_cu;  /* persistent blocks per compute unit of the H.v kernel          */
+    int32_t limits_bits;    /* index_mode 1: state bits after the top block used in the Limits key    */
+    int32_t index_mode;     /* 0 = hash-slot index with the input amplitude stored beside the key;
+                               1 = the paper's Limits ranges plus binary search of the sorted states    */
+    int32_t block_threads;  /* threads per block of the H.v kernel (64..1024, multiple of 64)            */
+    int32_t blocks_per_cu;  /* persistent blocks per compute unit of the H.v kernel                      */
+    int32_t chunk_bits;     /* width of the substate chunks of the symmetry-action table (1..16)         */
+    int32_t hash_load_pct;  /* index_mode 0: maximum load factor of the slot table in percent (10..90)   */
+    int32_t table_entry_bytes; /* 1, 2 or 4 bytes per symmetry-action entry (wide ones carry the block
+                                  position); 0 = automatic                                              */
 } ed_tuning_t;
 
 typedef struct ed_tables ed_tables_t;   /* host-side sublattice-coding tables */
@@ -110,10 +115,13 @@ typedef struct {
     int64_t dim;                /* sector dimension D                          */
     int32_t is_complex;
     int32_t n_sites, n_up, n_sublat, sub_bits, n_elems, n_bonds;
-    int32_t limits_bits;        /* key bits after the top block                */
-    int64_t n_keys;             /* Limits entries - 1                          */
-    int32_t table_lds;          /* 1 if the action table is staged in LDS      */
-    int32_t lds_bytes;          /* LDS bytes per block of the H.v kernel       */
+    int32_t index_mode;         /* 0 hash slots, 1 Limits + binary search       */
+    int32_t limits_bits;        /* key bits after the top block (index_mode 1) */
+    int64_t n_keys;             /* Limits entries - 1 (index_mode 1)           */
+    int64_t n_slots;            /* slot-table size (index_mode 0)              */
+    int32_t chunk_bits;         /* substate chunk width of the action table    */
+    int32_t table_entry_bytes;  /* bytes per action-table entry                */
+    int32_t lds_bytes;          /* LDS bytes of the staged tables per block    */
     int64_t device_bytes;       /* device memory owned by the handle           */
     double build_ms;            /* wall time of ed_build_basis                 */
 } ed_basis_info_t;

@@ -43,8 +43,10 @@ class ed_irrep_t(ctypes.Structure):
 
 
 class ed_tuning_t(ctypes.Structure):
-    _fields_ = [("limits_bits", ctypes.c_int32), ("table_lds", ctypes.c_int32),
-                ("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+    _fields_ = [("limits_bits", ctypes.c_int32), ("index_mode", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("chunk_bits", ctypes.c_int32), ("hash_load_pct", ctypes.c_int32),
+                ("table_entry_bytes", ctypes.c_int32)]
 
 
 class ed_tables_info_t(ctypes.Structure):
@@ -57,8 +59,10 @@ class ed_tables_info_t(ctypes.Structure):
 class ed_basis_info_t(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int64), ("is_complex", ctypes.c_int32), ("n_sites", ctypes.c_int32),
                 ("n_up", ctypes.c_int32), ("n_sublat", ctypes.c_int32), ("sub_bits", ctypes.c_int32),
-                ("n_elems", ctypes.c_int32), ("n_bonds", ctypes.c_int32), ("limits_bits", ctypes.c_int32),
-                ("n_keys", ctypes.c_int64), ("table_lds", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
+                ("n_elems", ctypes.c_int32), ("n_bonds", ctypes.c_int32), ("index_mode", ctypes.c_int32),
+                ("limits_bits", ctypes.c_int32), ("n_keys", ctypes.c_int64), ("n_slots", ctypes.c_int64),
+                ("chunk_bits", ctypes.c_int32), ("table_entry_bytes", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double)]
 
 
@@ -213,8 +217,10 @@ def ed_build_basis(arrays: ModelArrays, n_up, tuning=None, stream=None):
     h = ctypes.c_void_p()
     tn = None
     if tuning is not None:
-        tn = ed_tuning_t(int(tuning.get("limits_bits", 0)), int(tuning.get("table_lds", 0)),
-                         int(tuning.get("block_threads", 0)), int(tuning.get("blocks_per_cu", 0)))
+        tn = ed_tuning_t(int(tuning.get("limits_bits", 0)), int(tuning.get("index_mode", 0)),
+                         int(tuning.get("block_threads", 0)), int(tuning.get("blocks_per_cu", 0)),
+                         int(tuning.get("chunk_bits", 0)), int(tuning.get("hash_load_pct", 0)),
+                         int(tuning.get("table_entry_bytes", 0)))
     check(lib().ed_build_basis(lat, grp, irr, int(n_up), ctypes.byref(tn) if tn is not None else None,
                                stream, ctypes.byref(h)))
     return h

@@ -70,7 +70,7 @@ int ed_tables_info(const ed_tables_t *tt, ed_tables_info_t *info)
     info->n_perms = t.nu;
     info->rep_entries = (int64_t)t.rep.size();
     info->sym_entries = (int64_t)t.sym_list.size();
-    info->action_bytes = (int64_t)t.act.size() * (t.m <= 8 ? 1 : 2);
+    info->action_bytes = (int64_t)t.act.size() * (t.m <= 8 ? 1 : 2);   /* unchunked, one entry per substate */
     info->max_sym_len = t.max_sym;
     info->n_top = (int32_t)t.top_vals.size();
     return ED_OK;
@@ -129,6 +129,13 @@ int ed_build_basis(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irre
         delete b;
         return set_error(ED_ERR_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
     }
+    if (b->tuning.index_mode < 0 || b->tuning.index_mode > 1 || b->tuning.chunk_bits < 0 ||
+        b->tuning.chunk_bits > 16 || b->tuning.hash_load_pct < 0 || b->tuning.hash_load_pct > 90 ||
+        (b->tuning.table_entry_bytes != 0 && b->tuning.table_entry_bytes != 1 && b->tuning.table_entry_bytes != 2 &&
+         b->tuning.table_entry_bytes != 4)) {
+        delete b;
+        return set_error(ED_ERR_ARG, "tuning fields out of range");
+    }
     const ed::Tables &t = b->t;
     b->n_up = n_up;
     (void)hipGetDevice(&b->device);
@@ -168,6 +175,7 @@ void ed_free_basis(ed_basis_t *b)
 {
     if (!b) return;
     (void)hipDeviceSynchronize();
+    ed::free_lanczos_workspace(b);
     for (void *p : b->allocs) (void)hipFree(p);
     delete b;
 }
@@ -188,9 +196,12 @@ int ed_basis_info(const ed_basis_t *b, ed_basis_info_t *info)
     info->sub_bits = b->t.m;
     info->n_elems = b->t.ng;
     info->n_bonds = b->t.nb;
+    info->index_mode = b->db.index_mode;
     info->limits_bits = b->db.key_bits;
     info->n_keys = b->db.n_keys;
-    info->table_lds = b->dm.act_in_lds;
+    info->n_slots = b->n_slots;
+    info->chunk_bits = b->dm.chunk_bits;
+    info->table_entry_bytes = b->dm.act_bytes;
     info->lds_bytes = (int32_t)b->dm.lds_total;
     info->device_bytes = b->device_bytes;
     info->build_ms = b->build_ms;

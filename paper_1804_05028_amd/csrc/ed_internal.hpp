@@ -57,28 +57,45 @@ int build_tables(const ed_lattice_t *lat, const ed_group_t *grp, Tables &t);
 std::vector<uint32_t> divisors_of(uint32_t n);
 
 // Device-side description of the tables handed to kernels.  All tables live
-// in one device blob whose layout is the LDS image (byte offsets below); the
-// symmetry-action table is last so that it can stay in global memory when it
-// does not fit the LDS budget.
+// in one device blob whose layout is the LDS image (byte offsets below); every
+// block of the H.v and basis kernels stages the whole image in LDS.
+//   rep  : uint32 [ns][P]  low 16 bits Rep_X(s), high 16 bits offset of Sym_X(s)
+//   sym  : uint32 lists [count, e_1, ..., e_count], ascending g, with
+//          e = g | distinct-permutation index << 16 | flip << 31
+//   act  : AT [nu][ns][nc][2^c]  image pattern of one c-bit chunk of a substate;
+//          2- and 4-byte entries of chunk 0 also hold the target block index
+//   shift: uint8 [nu][ns]  bit position of the image block
+//   chi  : double [ng] (real sectors) or double2 [ng] (complex sectors)
+//   div  : double [n_div] sqrt of the divisors of |G|, then their inverses
+//   bonds: {uint64 mask, double J/2} [nb]
+//   rank : uint16 [P]      rank of a top-block value (Limits index only)
 struct DevModel {
     int N, ns, m, ng, nu, nb;
     uint32_t P;
     int is_complex;
     int trivial_irrep;
     int n_div;
-    const char *blob;          // device blob
-    uint32_t lds_rep, lds_sym_off, lds_sym_list, lds_act, lds_u_shift, lds_g_u, lds_g_flip, lds_chi,
-        lds_div, lds_bonds, lds_total;
-    int act_in_lds;
+    int chunk_bits, n_chunks;
+    int act_bytes;             // 1, 2 or 4 bytes per action-table entry
+    const char *blob;
+    uint32_t off_rep, off_sym, off_act, off_shift, off_chi, off_div, off_divval, off_bonds, off_rank,
+        lds_total;
 };
 
 struct DevBasis {
     int64_t dim;
     const uint64_t *states;    // packed entries [dim]
+    int index_mode;            // 0 hash slots, 1 Limits + binary search
+    // Limits index (Alg. "Parallel matrix-vector multiply", receiving step)
     const uint32_t *limits;    // [n_keys + 1]
     int64_t n_keys;
     int key_bits;              // q
     int key_shift;             // N - m - q
+    // hash-slot index: 16-byte (real) or 32-byte (complex) slots
+    // {packed state, amplitude}; open addressing with linear probing
+    char *slots;
+    int slot_log2;             // number of slots = 2^slot_log2
+    const uint32_t *slot_of;   // [dim] slot index of every representative
 };
 
 }  // namespace ed
@@ -102,7 +119,16 @@ struct ed_basis {
     int stats_valid = 0;
     int64_t n_kept = 0, n_dropped = 0;
     int grid_blocks = 0;
+    int64_t n_slots = 0;
     std::vector<double> J_cache;   // couplings currently written into the blob
+    // Lanczos workspace, kept between calls and freed with the handle
+    struct {
+        double *vec[3] = {nullptr, nullptr, nullptr};
+        double *partials = nullptr, *ahist = nullptr, *bhist = nullptr, *svec = nullptr;
+        void *state = nullptr;
+        int cap_steps = 0;
+        size_t cap_partials = 0;
+    } lzw;
 };
 
 namespace ed {
@@ -115,5 +141,6 @@ int launch_backward_J(const ed_basis *b, const double *J, const void *x, const v
 int run_lanczos(const ed_basis *b, const double *J, const void *v0, int n_steps, double *alpha, double *beta,
                 int *n_done, void *psi0, void *stream);
 int device_alloc(ed_basis *b, void **p, size_t bytes);
+void free_lanczos_workspace(ed_basis *b);
 const char *last_error();
 }  // namespace ed

@@ -3,17 +3,20 @@
 //
 // Data layout in HBM
 //   states[D]   uint64: bits [0,56) representative, bits [56,64) index of its
-//               stabiliser size among the divisors of |G| (the norm is read
-//               in the same load that confirms the index lookup).
-//   limits[K+1] uint32: begin offset of every key (top-block rank, next q bits).
-//   x, y[D]     double (or double2 for complex sectors), ascending-rep order.
-// Small lookup tables (Rep_X, Sym_X, the symmetry action when it fits, the
-// group-element descriptors, characters, bonds) are staged once per
-// persistent block in LDS.
+//               stabiliser size among the divisors of |G|.
+//   slots       hash-slot index (default): open addressing with linear probing
+//               over 16-byte slots {packed state, x} (complex: 32-byte slots
+//               {packed state, -, re, im}) at a low load factor; the input
+//               vector is scattered into the slots before each H.v, so that one
+//               16-byte read usually returns the index check, the norm and the
+//               amplitude of a target together.
+//   limits[K+1] uint32: the paper's Limits ranges (index mode 1): begin offset
+//               of every key (top-block rank, next q bits), then binary search.
+//   x, y[D]     double (or double2), ascending-representative order.
+// All lookup tables are staged once per persistent block in LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -30,87 +33,130 @@ namespace ed {
 
 constexpr int kMaxBondWords = 4;   // up to 256 bonds
 constexpr int kWave = 64;
+constexpr uint64_t kEmpty = ~0ull;  // empty slot key (norm index 255 never occurs)
 
-// ---------------------------------------------------------------------------
-// LDS staging
-// ---------------------------------------------------------------------------
+enum { IDX_HASH = 0, IDX_LIMITS = 1 };
 
 struct BondLds {
     uint64_t mask;     // both sites of the bond
     double jhalf;      // J_b / 2
 };
 
-// Pointers into LDS (or global memory for a table that does not fit).
+// ---------------------------------------------------------------------------
+// LDS staging
+// ---------------------------------------------------------------------------
 template <typename AT>
 struct Ctx {
-    int N, ns, m;
-    uint32_t mmask;
+    int N, ns, m, cb, nc;
+    uint32_t mmask, cmask;
     uint64_t low_mask;           // state bits below the top block
-    const uint32_t *rep;         // [ns][P]
-    const uint32_t *sym_off;     // [ns][P+1]
-    const uint16_t *sym_list;
-    const AT *act;               // [nu][ns][P]
-    const uint8_t *u_shift;      // [nu][ns]
-    const uint16_t *g_u;         // [ng]
-    const uint8_t *g_flip;       // [ng]
-    const double *chi;           // [ng][2]
-    const double *div_sqrt;      // [n_div]
-    const double *div_rsqrt;     // [n_div]
-    const BondLds *bonds;        // [nb]
+    const uint32_t *rep;
+    const uint32_t *sym;         // [count, e_1, ...], e = g | u << 16 | flip << 31
+    const AT *act;
+    const uint8_t *shift;
+    const double *chi;           // [ng] real, or [ng][2] complex
+    const double *div_sqrt;
+    const double *div_rsqrt;
+    const uint32_t *div_val;
+    const BondLds *bonds;
+    const uint16_t *rank;
 };
 
 __device__ __forceinline__ void lds_copy(char *dst, const void *src, uint32_t bytes)
 {
-    const uint32_t *s = (const uint32_t *)src;
-    uint32_t *d = (uint32_t *)dst;
-    for (uint32_t k = threadIdx.x; k < bytes / 4; k += blockDim.x) d[k] = s[k];
+    const uint4 *s = (const uint4 *)src;
+    uint4 *d = (uint4 *)dst;
+    for (uint32_t k = threadIdx.x; k < bytes / 16; k += blockDim.x) d[k] = s[k];
 }
 
-// The host packs every table into one device blob with the same layout as the
-// LDS image, so staging is one contiguous copy.
-template <typename AT, bool ACT_LDS>
-__device__ __forceinline__ Ctx<AT> stage(const DevModel &dm, const char *blob, char *lds)
+template <typename AT>
+__device__ __forceinline__ Ctx<AT> stage(const DevModel &dm, char *lds)
 {
-    lds_copy(lds, blob, dm.lds_total);
+    lds_copy(lds, dm.blob, dm.lds_total);
     __syncthreads();
     Ctx<AT> c;
     c.N = dm.N;
     c.ns = dm.ns;
     c.m = dm.m;
+    c.cb = dm.chunk_bits;
+    c.nc = dm.n_chunks;
     c.mmask = dm.P - 1;
+    c.cmask = (1u << dm.chunk_bits) - 1u;
     c.low_mask = (dm.N - dm.m >= 64) ? ~0ull : ((1ull << (dm.N - dm.m)) - 1ull);
-    c.rep = (const uint32_t *)(lds + dm.lds_rep);
-    c.sym_off = (const uint32_t *)(lds + dm.lds_sym_off);
-    c.sym_list = (const uint16_t *)(lds + dm.lds_sym_list);
-    c.act = ACT_LDS ? (const AT *)(lds + dm.lds_act) : (const AT *)(dm.blob + dm.lds_act);
-    c.u_shift = (const uint8_t *)(lds + dm.lds_u_shift);
-    c.g_u = (const uint16_t *)(lds + dm.lds_g_u);
-    c.g_flip = (const uint8_t *)(lds + dm.lds_g_flip);
-    c.chi = (const double *)(lds + dm.lds_chi);
-    c.div_sqrt = (const double *)(lds + dm.lds_div);
+    c.rep = (const uint32_t *)(lds + dm.off_rep);
+    c.sym = (const uint32_t *)(lds + dm.off_sym);
+    c.act = (const AT *)(lds + dm.off_act);
+    c.shift = (const uint8_t *)(lds + dm.off_shift);
+    c.chi = (const double *)(lds + dm.off_chi);
+    c.div_sqrt = (const double *)(lds + dm.off_div);
     c.div_rsqrt = c.div_sqrt + dm.n_div;
-    c.bonds = (const BondLds *)(lds + dm.lds_bonds);
+    c.div_val = (const uint32_t *)(lds + dm.off_divval);
+    c.bonds = (const BondLds *)(lds + dm.off_bonds);
+    c.rank = (const uint16_t *)(lds + dm.off_rank);
     return c;
 }
 
+// Action-table entries: uint8 holds the image pattern only (its block
+// position comes from the shift table); uint16 / uint32 entries of chunk 0
+// also carry the target block index above bit 12 / 16, which saves that
+// lookup.
+template <typename AT>
+struct ActTraits {
+    static constexpr bool kPos = sizeof(AT) > 1;
+    static constexpr int kPosShift = sizeof(AT) == 2 ? 12 : 16;
+};
+
+template <typename AT>
+__device__ __forceinline__ uint64_t place_block(const Ctx<AT> &c, uint32_t u, int ns, int X, uint32_t e)
+{
+    if (ActTraits<AT>::kPos) {
+        const uint32_t img = e & ((1u << ActTraits<AT>::kPosShift) - 1u);
+        const int pos = (int)(e >> ActTraits<AT>::kPosShift);
+        return (uint64_t)img << (c.N - (pos + 1) * c.m);
+    }
+    return (uint64_t)e << c.shift[u * ns + X];
+}
+
+// image of block X of s under the permutation u (chunked action table)
+template <typename AT>
+__device__ __forceinline__ uint32_t block_image(const Ctx<AT> &c, uint32_t u, int X, uint32_t sx)
+{
+    const AT *t = c.act + ((size_t)(u * c.ns + X) * c.nc << c.cb);
+    uint32_t v = 0;
+    for (int k = 0; k < c.nc; ++k) v |= t[(k << c.cb) | ((sx >> (k * c.cb)) & c.cmask)];
+    return v;
+}
+
+// all blocks except Y of g s, placed at their target positions, flip applied
+template <typename AT>
+__device__ __forceinline__ uint64_t image_below_top(const Ctx<AT> &c, uint32_t u, uint32_t fl, int Y, uint64_t s)
+{
+    uint64_t v = 0;
+    for (int X = 0; X < c.ns; ++X) {
+        if (X == Y) continue;
+        const uint32_t sx = (uint32_t)(s >> (c.N - (X + 1) * c.m)) & c.mmask;
+        v |= place_block(c, u, c.ns, X, block_image(c, u, X, sx));
+    }
+    if (fl) v ^= c.low_mask;
+    return v;
+}
+
 // ---------------------------------------------------------------------------
-// Alg. "Sublattice coding algorithm for finding the representative"
-//   MinRep = min_X Rep_X(s_X); for every block Y attaining it and every
-//   g in Sym_Y(s_Y), assemble g s from the per-block action table and keep
-//   the strict minimum.  The top block of every candidate equals MinRep, so
-//   only the other blocks are assembled.  Returns the representative, the
-//   first minimising group element, and the packed rep-table entry of MinRep
-//   (rank << 16 | value) used for the index key.
+// Alg. "Sublattice coding algorithm for finding the representative":
+//   MinRep = min_X Rep_X(s_X); for every block Y attaining it and every g in
+//   Sym_Y(s_Y), assemble g s from the per-block action table and keep the
+//   strict minimum.  The top block of every candidate is MinRep itself, so
+//   only the other blocks are assembled.
 // ---------------------------------------------------------------------------
 template <typename AT>
-__device__ __forceinline__ uint64_t find_rep(const Ctx<AT> &c, uint64_t s, uint32_t &g_best, uint32_t &min_ent)
+__device__ __forceinline__ uint64_t find_rep(const Ctx<AT> &c, uint64_t s, uint32_t &g_best, uint32_t &min_val)
 {
     const int N = c.N, m = c.m, ns = c.ns;
     const uint32_t P = c.mmask + 1;
     uint32_t minr = 0xFFFFFFFFu, tie = 0;
     for (int X = 0; X < ns; ++X) {
-        uint32_t sx = (uint32_t)(s >> (N - (X + 1) * m)) & c.mmask;
-        uint32_t r = c.rep[X * P + sx];
+        const uint32_t sx = (uint32_t)(s >> (N - (X + 1) * m)) & c.mmask;
+        const uint32_t r = c.rep[X * P + sx] & 0xFFFFu;
         if (r < minr) {
             minr = r;
             tie = 1u << X;
@@ -118,27 +164,19 @@ __device__ __forceinline__ uint64_t find_rep(const Ctx<AT> &c, uint64_t s, uint3
             tie |= 1u << X;
         }
     }
-    const uint64_t top = (uint64_t)(minr & 0xFFFFu) << (N - m);
+    const uint64_t top = (uint64_t)minr << (N - m);
     uint64_t best = ~0ull;
     uint32_t bg = 0;
     while (tie) {
         const int Y = __builtin_ctz(tie);
         tie &= tie - 1;
         const uint32_t sy = (uint32_t)(s >> (N - (Y + 1) * m)) & c.mmask;
-        const uint32_t k0 = c.sym_off[Y * (P + 1) + sy], k1 = c.sym_off[Y * (P + 1) + sy + 1];
-        for (uint32_t k = k0; k < k1; ++k) {
-            const uint32_t g = c.sym_list[k];
-            const uint32_t u = c.g_u[g];
-            const AT *au = c.act + (size_t)u * ns * P;
-            const uint8_t *sh = c.u_shift + u * ns;
-            uint64_t v = 0;
-            for (int X = 0; X < ns; ++X) {
-                if (X == Y) continue;
-                uint32_t sx = (uint32_t)(s >> (N - (X + 1) * m)) & c.mmask;
-                v |= (uint64_t)au[X * P + sx] << sh[X];
-            }
-            if (c.g_flip[g]) v ^= c.low_mask;
-            v |= top;
+        const uint32_t off = c.rep[Y * P + sy] >> 16;
+        const uint32_t cnt = c.sym[off];
+        for (uint32_t k = 1; k <= cnt; ++k) {
+            const uint32_t ent = c.sym[off + k];
+            const uint32_t g = ent & 0xFFFFu;
+            const uint64_t v = image_below_top(c, (ent >> 16) & 0x7FFFu, ent >> 31, Y, s) | top;
             if (v < best) {
                 best = v;
                 bg = g;
@@ -146,21 +184,127 @@ __device__ __forceinline__ uint64_t find_rep(const Ctx<AT> &c, uint64_t s, uint3
         }
     }
     g_best = bg;
-    min_ent = minr;
+    min_val = minr;
     return best;
 }
 
-// Index lookup (Alg. "Parallel matrix-vector multiply", receiving step):
-// Limits(key) -> [begin, end), then binary search of the ascending states.
-// Returns the position or -1; *entry receives the packed entry found.
-__device__ __forceinline__ int64_t lookup(const DevBasis &b, uint64_t rep, uint32_t min_ent, uint64_t &entry)
+// The same search with the number of sublattices fixed at compile time: the
+// substate blocks stay in registers and the block loops unroll.
+template <typename AT, int NS>
+__device__ __forceinline__ uint64_t find_rep_ns(const Ctx<AT> &c, uint64_t s, uint32_t &g_best)
 {
-    const uint64_t key = ((uint64_t)(min_ent >> 16) << b.key_bits) |
-                         ((rep >> b.key_shift) & ((1ull << b.key_bits) - 1ull));
-    uint32_t lo = b.limits[key], hi = b.limits[key + 1];
+    const int N = c.N, m = c.m;
+    const uint32_t P = c.mmask + 1;
+    uint32_t sx[NS];
+    uint32_t minr = 0xFFFFFFFFu;
+#pragma unroll
+    for (int X = 0; X < NS; ++X) {
+        sx[X] = (uint32_t)(s >> (N - (X + 1) * m)) & c.mmask;
+        minr = min(minr, c.rep[X * P + sx[X]] & 0xFFFFu);
+    }
+    uint32_t tie = 0;
+#pragma unroll
+    for (int X = 0; X < NS; ++X) tie |= (uint32_t)((c.rep[X * P + sx[X]] & 0xFFFFu) == minr) << X;
+    const uint64_t top = (uint64_t)minr << (N - m);
+    uint64_t best = ~0ull;
+    uint32_t bg = 0;
+    while (tie) {
+        const int Y = __builtin_ctz(tie);
+        tie &= tie - 1;
+        const uint32_t sy = (uint32_t)(s >> (N - (Y + 1) * m)) & c.mmask;
+        const uint32_t off = c.rep[Y * P + sy] >> 16;
+        const uint32_t cnt = c.sym[off];
+        for (uint32_t k = 1; k <= cnt; ++k) {
+            const uint32_t ent = c.sym[off + k];
+            const uint32_t u = (ent >> 16) & 0x7FFFu;
+            const AT *tu = c.act + ((size_t)u * NS * c.nc << c.cb);
+            uint64_t v = 0;
+#pragma unroll
+            for (int X = 0; X < NS; ++X) {
+                if (X == Y) continue;
+                const AT *t = tu + ((X * c.nc) << c.cb);
+                uint32_t blk = 0;
+                for (int k2 = 0; k2 < c.nc; ++k2) blk |= t[(k2 << c.cb) | ((sx[X] >> (k2 * c.cb)) & c.cmask)];
+                v |= place_block(c, u, NS, X, blk);
+            }
+            if (ent >> 31) v ^= c.low_mask;
+            v |= top;
+            if (v < best) {
+                best = v;
+                bg = ent & 0xFFFFu;
+            }
+        }
+    }
+    g_best = bg;
+    return best;
+}
+
+template <typename AT, int NS>
+__device__ __forceinline__ uint64_t rep_search(const Ctx<AT> &c, uint64_t s, uint32_t &g)
+{
+    if (NS > 0) return find_rep_ns<AT, (NS > 0 ? NS : 1)>(c, s, g);
+    uint32_t mv;
+    return find_rep(c, s, g, mv);
+}
+
+// ---------------------------------------------------------------------------
+// index lookups
+// ---------------------------------------------------------------------------
+// home slot of a state: MurmurHash3's 64-bit finaliser (Appleby), top bits
+__device__ __forceinline__ uint64_t slot_of_state(uint64_t s, int log2n)
+{
+    s ^= s >> 33;
+    s *= 0xff51afd7ed558ccdull;
+    s ^= s >> 33;
+    s *= 0xc4ceb9fe1a85ec53ull;
+    s ^= s >> 33;
+    return log2n ? (s >> (64 - log2n)) : 0ull;
+}
+
+// first 16 bytes of a slot: {key, x} (real) or {key, -} (complex)
+template <bool CPLX>
+__device__ __forceinline__ ulonglong2 load_slot(const char *slots, uint64_t sl)
+{
+    return *(const ulonglong2 *)(slots + (sl << (CPLX ? 5 : 4)));
+}
+
+// Probe from the home slot (whose first 16 bytes are q) until the target or
+// an empty slot; returns 1 and the packed key and amplitude if found.
+template <bool CPLX>
+__device__ __forceinline__ int resolve_slot(const DevBasis &db, ulonglong2 q, uint64_t sl, uint64_t target,
+                                            uint64_t &key, double &vr, double &vi)
+{
+    const uint64_t smask = (1ull << db.slot_log2) - 1ull;
+    while (true) {
+        if (q.x == kEmpty) return 0;
+        if ((q.x & kStateMask) == target) {
+            key = q.x;
+            if (CPLX) {
+                const double2 v = *(const double2 *)(db.slots + (sl << 5) + 16);
+                vr = v.x;
+                vi = v.y;
+            } else {
+                vr = __longlong_as_double((long long)q.y);
+                vi = 0.0;
+            }
+            return 1;
+        }
+        sl = (sl + 1) & smask;
+        q = load_slot<CPLX>(db.slots, sl);
+    }
+}
+
+// the paper's index: Limits(key) -> [begin, end), binary search of the states
+template <typename AT>
+__device__ __forceinline__ int64_t lookup_limits(const Ctx<AT> &c, const DevBasis &db, uint64_t rep, uint32_t min_val,
+                                                 uint64_t &entry)
+{
+    const uint64_t key = ((uint64_t)c.rank[min_val] << db.key_bits) |
+                         ((rep >> db.key_shift) & ((1ull << db.key_bits) - 1ull));
+    uint32_t lo = db.limits[key], hi = db.limits[key + 1];
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        const uint64_t e = b.states[mid];
+        const uint64_t e = db.states[mid];
         const uint64_t sv = e & kStateMask;
         if (sv == rep) {
             entry = e;
@@ -182,16 +326,6 @@ struct Scalar<true> {
     using T = double2;
 };
 
-__device__ __forceinline__ double load_x(const double *x, int64_t j) { return x[j]; }
-__device__ __forceinline__ double2 load_x(const double2 *x, int64_t j) { return x[j]; }
-
-// ---------------------------------------------------------------------------
-// Row kernel of H.v (gather form of the parallel matrix-vector multiply):
-//   y_i = d_i x_i + sum_{b antiparallel} (J_b/2) chi(g) sqrt(n_j/n_i) x_j
-// one thread per row, persistent blocks, every y_i written once.
-// MODE 0: y = H x.   MODE 1: count kept/dropped terms.
-// MODE 2: Lanczos w = H v - beta_prev v_prev, with per-block <v, w> partials.
-// ---------------------------------------------------------------------------
 struct LzState {
     int j;              // step index
     int done;           // breakdown or finished
@@ -199,69 +333,146 @@ struct LzState {
     double alpha_cur, beta_cur, beta_prev;
 };
 
-template <bool CPLX, typename AT, bool ACT_LDS, int MODE>
-__global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const char *blob,
-                                                const typename Scalar<CPLX>::T *__restrict__ x,
-                                                typename Scalar<CPLX>::T *__restrict__ y,
-                                                const typename Scalar<CPLX>::T *__restrict__ vprev,
-                                                double *partials, unsigned long long *stats,
-                                                const LzState *lz, double jsum_quarter)
+template <bool CPLX, typename AT>
+__device__ __forceinline__ void chi_of(const Ctx<AT> &c, uint32_t g, double &cr, double &ci)
 {
-    using T = typename Scalar<CPLX>::T;
+    if (CPLX) {
+        cr = c.chi[2 * g];
+        ci = c.chi[2 * g + 1];
+    } else {
+        cr = c.chi[g];
+        ci = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// H.v, gather form of the parallel matrix-vector multiply:
+//   y_i = d_i x_i + sum_{b antiparallel} (J_b/2) chi(g) sqrt(n_j/n_i) x_j
+// One thread per row, persistent blocks, every y_i written once.  NS > 0
+// fixes the number of sublattices at compile time (0: read it at run time).
+// MODE 0: y = H x.  MODE 1: count kept/dropped terms.  MODE 2: Lanczos
+// w = H v - beta_prev v_prev with per-block <v, w> partial sums.
+// ---------------------------------------------------------------------------
+// antiparallel bonds of a row, one bit per bond, in four named words so that
+// they stay in registers
+struct BondMask {
+    uint64_t w0, w1, w2, w3;
+};
+
+template <typename AT>
+__device__ __forceinline__ uint64_t bond_word(const Ctx<AT> &c, uint64_t s, int w, int nb)
+{
+    uint64_t am = 0;
+    const int bend = min(64, nb - 64 * w);
+    for (int k = 0; k < bend; ++k) {
+        const uint64_t bm = c.bonds[64 * w + k].mask;
+        const uint64_t t = s & bm;
+        am |= (uint64_t)((t != 0) & (t != bm)) << k;
+    }
+    return am;
+}
+
+__device__ __forceinline__ int pop_bond(BondMask &m)
+{
+    if (m.w0) {
+        const int k = __builtin_ctzll(m.w0);
+        m.w0 &= m.w0 - 1;
+        return k;
+    }
+    if (m.w1) {
+        const int k = __builtin_ctzll(m.w1);
+        m.w1 &= m.w1 - 1;
+        return 64 + k;
+    }
+    if (m.w2) {
+        const int k = __builtin_ctzll(m.w2);
+        m.w2 &= m.w2 - 1;
+        return 128 + k;
+    }
+    const int k = __builtin_ctzll(m.w3);
+    m.w3 &= m.w3 - 1;
+    return 192 + k;
+}
+
+template <bool CPLX, typename AT, int INDEX, int MODE, int NS>
+__global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const typename Scalar<CPLX>::T *__restrict__ x,
+                                                typename Scalar<CPLX>::T *__restrict__ y,
+                                                const typename Scalar<CPLX>::T *__restrict__ vprev, double *partials,
+                                                unsigned long long *stats, const LzState *lz, double jsum_quarter)
+{
     extern __shared__ __align__(16) char lds[];
     if (MODE == 2 && lz->done) return;
-    const Ctx<AT> c = stage<AT, ACT_LDS>(dm, blob, lds);
+    const Ctx<AT> c = stage<AT>(dm, lds);
     const int nb = dm.nb;
-    const int nw = (nb + 63) >> 6;
     const int64_t D = db.dim;
     double acc_part = 0.0;
     unsigned long long kept = 0, dropped = 0;
     const double beta_prev = (MODE == 2) ? lz->beta_prev : 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t e = db.states[i];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // wave-uniform row loop: every lane of a wave runs the same iterations
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < D; i0 += stride) {
+        const int64_t i = i0 + lane;
+        const bool row_ok = i < D;
+        const uint64_t e = row_ok ? db.states[i] : 0ull;
         const uint64_t s = e & kStateMask;
         const double rs_i = c.div_rsqrt[e >> kNormShift];
-        double anti_sum = 0.0;
-        double ar = 0.0, ai = 0.0;
-        for (int w = 0; w < kMaxBondWords; ++w) {
-            if (w >= nw) break;
-            // antiparallel bonds of this word
-            uint64_t am = 0;
-            const int bend = min(64, nb - 64 * w);
-            for (int k = 0; k < bend; ++k) {
-                const uint64_t bm = c.bonds[64 * w + k].mask;
-                const uint64_t t = s & bm;
-                am |= (uint64_t)((t != 0) & (t != bm)) << k;
-            }
-            while (am) {
-                const int k = __builtin_ctzll(am);
-                am &= am - 1;
-                const BondLds bd = c.bonds[64 * w + k];
+        double anti_sum = 0.0, ar = 0.0, ai = 0.0;
+        // antiparallel bonds of this row
+        BondMask am;
+        am.w0 = bond_word(c, s, 0, nb);
+        am.w1 = nb > 64 ? bond_word(c, s, 1, nb) : 0ull;
+        am.w2 = nb > 128 ? bond_word(c, s, 2, nb) : 0ull;
+        am.w3 = nb > 192 ? bond_word(c, s, 3, nb) : 0ull;
+        const int n_terms = row_ok ? __popcll(am.w0) + __popcll(am.w1) + __popcll(am.w2) + __popcll(am.w3) : 0;
+        if (INDEX == IDX_HASH) {
+            for (int term = 0; term < n_terms; ++term) {
+                const BondLds bd = c.bonds[pop_bond(am)];
                 anti_sum += bd.jhalf;
-                const uint64_t sp = s ^ bd.mask;
-                uint32_t g, ment;
-                const uint64_t r = find_rep(c, sp, g, ment);
-                uint64_t ej = 0;
-                const int64_t j = lookup(db, r, ment, ej);
-                if (MODE == 1) {
-                    if (j >= 0) ++kept; else ++dropped;
+                uint32_t g;
+                const uint64_t r = rep_search<AT, NS>(c, s ^ bd.mask, g);
+                const uint64_t sl = slot_of_state(r, db.slot_log2);
+                uint64_t key;
+                double vr, vi;
+                if (!resolve_slot<CPLX>(db, load_slot<CPLX>(db.slots, sl), sl, r, key, vr, vi)) {
+                    ++dropped;
                     continue;
                 }
-                if (j < 0) continue;
-                const double amp = bd.jhalf * c.div_sqrt[ej >> kNormShift] * rs_i;
+                ++kept;
+                if (MODE == 1) continue;
+                double cr, ci;
+                chi_of<CPLX>(c, g, cr, ci);
+                const double amp = bd.jhalf * rs_i * c.div_sqrt[key >> kNormShift];
+                ar += amp * (cr * vr - ci * vi);
+                if (CPLX) ai += amp * (cr * vi + ci * vr);
+            }
+        } else {
+            for (int term = 0; term < n_terms; ++term) {
+                const BondLds bd = c.bonds[pop_bond(am)];
+                anti_sum += bd.jhalf;
+                uint32_t g, mval;
+                const uint64_t r = find_rep(c, s ^ bd.mask, g, mval);
+                uint64_t ej = 0;
+                const int64_t j = lookup_limits(c, db, r, mval, ej);
+                if (j < 0) {
+                    ++dropped;
+                    continue;
+                }
+                ++kept;
+                if (MODE == 1) continue;
+                double cr, ci;
+                chi_of<CPLX>(c, g, cr, ci);
+                const double amp = bd.jhalf * rs_i * c.div_sqrt[ej >> kNormShift];
                 if (CPLX) {
-                    const T xj = load_x(x, j);
-                    const double cr = amp * c.chi[2 * g], ci = amp * c.chi[2 * g + 1];
-                    const double2 xv = *(const double2 *)&xj;
-                    ar += cr * xv.x - ci * xv.y;
-                    ai += cr * xv.y + ci * xv.x;
+                    const double2 xv = *(const double2 *)&x[j];
+                    ar += amp * (cr * xv.x - ci * xv.y);
+                    ai += amp * (cr * xv.y + ci * xv.x);
                 } else {
-                    const double xj = *(const double *)&x[j];
-                    ar += amp * c.chi[2 * g] * xj;
+                    ar += amp * cr * *(const double *)&x[j];
                 }
             }
         }
-        if (MODE == 1) continue;
+        if (MODE == 1 || !row_ok) continue;
         const double d = jsum_quarter - anti_sum;
         if (CPLX) {
             const double2 xi = *(const double2 *)&x[i];
@@ -290,7 +501,7 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
         atomicAdd(&stats[1], dropped);
     }
     if (MODE == 2) {
-        // deterministic block reduction in LDS (tables are no longer needed)
+        // deterministic block reduction in LDS (the tables are no longer needed)
         __syncthreads();
         double *red = (double *)lds;
         red[threadIdx.x] = acc_part;
@@ -303,10 +514,24 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
     }
 }
 
+// x -> value fields of the slot table (hash index); slot_of gives each
+// representative's slot
+__global__ void k_pack_real(const double *x, const uint32_t *slot_of, char *slots, int64_t D)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < D; j += (int64_t)gridDim.x * blockDim.x)
+        *(double *)(slots + (size_t)slot_of[j] * 16 + 8) = x[j];
+}
+
+__global__ void k_pack_cplx(const double2 *x, const uint32_t *slot_of, char *slots, int64_t D)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < D; j += (int64_t)gridDim.x * blockDim.x)
+        *(double2 *)(slots + (size_t)slot_of[j] * 32 + 16) = x[j];
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint, bond part: A_b = Re sum_i conj(gy_i) (dH/dJ_b x)_i.  Bonds are
 // visited in the same order by every lane so that each bond's contributions
-// can be summed across the wave (fixed tree order), then across waves and
+// are summed across the wave in a fixed tree order, then across waves and
 // blocks in fixed order: the result is deterministic.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v)
@@ -315,14 +540,13 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <bool CPLX, typename AT, bool ACT_LDS>
-__global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, const char *blob,
-                                                     const typename Scalar<CPLX>::T *__restrict__ x,
+template <bool CPLX, typename AT, int INDEX>
+__global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, const typename Scalar<CPLX>::T *__restrict__ x,
                                                      const typename Scalar<CPLX>::T *__restrict__ gy,
                                                      double *partials /* [grid][nb] */)
 {
     extern __shared__ __align__(16) char lds[];
-    const Ctx<AT> c = stage<AT, ACT_LDS>(dm, blob, lds);
+    const Ctx<AT> c = stage<AT>(dm, lds);
     const int nb = dm.nb;
     const int nwaves = blockDim.x / kWave;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -331,15 +555,12 @@ __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, c
     __syncthreads();
     const int64_t D = db.dim;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // every lane of a wave runs the same number of iterations
-    const int64_t wave_first = base - lane;
+    const int64_t wave_first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane;
     for (int64_t i0 = wave_first; i0 < D; i0 += stride) {
         const int64_t i = i0 + lane;
         const bool valid = i < D;
         uint64_t s = 0;
-        double rs_i = 0.0, gx_r = 0.0, gx_i = 0.0;   // conj(gy_i) * x_i
-        double g_r = 0.0, g_i = 0.0;
+        double rs_i = 0.0, gx_r = 0.0, g_r = 0.0, g_i = 0.0;   // gx_r = Re(conj(gy_i) x_i)
         if (valid) {
             const uint64_t e = db.states[i];
             s = e & kStateMask;
@@ -355,27 +576,44 @@ __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, c
                 gx_r = g_r * *(const double *)&x[i];
             }
         }
-        (void)gx_i;
         for (int b = 0; b < nb; ++b) {
             const BondLds bd = c.bonds[b];
             const uint64_t t = s & bd.mask;
             const bool anti = valid && (t != 0) && (t != bd.mask);
             double contrib = valid ? (anti ? -0.25 : 0.25) * gx_r : 0.0;
             if (anti) {
-                uint32_t g, ment;
-                const uint64_t r = find_rep(c, s ^ bd.mask, g, ment);
-                uint64_t ej = 0;
-                const int64_t j = lookup(db, r, ment, ej);
-                if (j >= 0) {
-                    const double amp = 0.5 * c.div_sqrt[ej >> kNormShift] * rs_i;
-                    const double cr = amp * c.chi[2 * g], ci = amp * c.chi[2 * g + 1];
-                    if (CPLX) {
-                        const double2 xv = *(const double2 *)&x[j];
-                        const double tr = cr * xv.x - ci * xv.y, ti = cr * xv.y + ci * xv.x;
-                        contrib += g_r * tr + g_i * ti;   // Re(conj(gy) t)
-                    } else {
-                        contrib += g_r * cr * *(const double *)&x[j];
+                uint32_t g, mval;
+                const uint64_t r = find_rep(c, s ^ bd.mask, g, mval);
+                double cr, ci;
+                chi_of<CPLX>(c, g, cr, ci);
+                bool found = false;
+                double sq = 0.0, vr = 0.0, vi = 0.0;
+                if (INDEX == IDX_HASH) {
+                    const uint64_t sl = slot_of_state(r, db.slot_log2);
+                    uint64_t key;
+                    if (resolve_slot<CPLX>(db, load_slot<CPLX>(db.slots, sl), sl, r, key, vr, vi)) {
+                        found = true;
+                        sq = c.div_sqrt[key >> kNormShift];
                     }
+                } else {
+                    uint64_t ej = 0;
+                    const int64_t j = lookup_limits(c, db, r, mval, ej);
+                    if (j >= 0) {
+                        found = true;
+                        sq = c.div_sqrt[ej >> kNormShift];
+                        if (CPLX) {
+                            const double2 xv = *(const double2 *)&x[j];
+                            vr = xv.x;
+                            vi = xv.y;
+                        } else {
+                            vr = *(const double *)&x[j];
+                        }
+                    }
+                }
+                if (found) {
+                    const double amp = 0.5 * sq * rs_i;
+                    const double tr = amp * (cr * vr - ci * vi), ti = amp * (cr * vi + ci * vr);
+                    contrib += g_r * tr + g_i * ti;   // Re(conj(gy) t)
                 }
             }
             const double wsum = wave_sum(contrib);
@@ -411,13 +649,12 @@ struct BuildParams {
     uint64_t n_prefix;
 };
 
-template <typename AT, bool ACT_LDS, bool EMIT>
-__global__ void __launch_bounds__(256) k_basis_enum(DevModel dm, BuildParams bp, const char *blob,
-                                                    uint32_t *counts, const uint64_t *offsets, uint64_t *out)
+template <typename AT, bool EMIT>
+__global__ void __launch_bounds__(256) k_basis_enum(DevModel dm, BuildParams bp, uint32_t *counts,
+                                                    const uint64_t *offsets, uint64_t *out)
 {
     extern __shared__ __align__(16) char lds[];
-    const Ctx<AT> c = stage<AT, ACT_LDS>(dm, blob, lds);
-    const uint32_t *div_val = (const uint32_t *)(c.div_rsqrt + dm.n_div);
+    const Ctx<AT> c = stage<AT>(dm, lds);
     const int N = c.N, m = c.m, ns = c.ns;
     const uint32_t P = c.mmask + 1;
     const int R = bp.R;
@@ -430,22 +667,26 @@ __global__ void __launch_bounds__(256) k_basis_enum(DevModel dm, BuildParams bp,
         bool ok = ((c.rep[t] & 0xFFFFu) == t) && r >= 0 && r <= R;
         // blocks entirely inside the prefix must not beat the top block
         for (int X = 1; ok && (X + 1) * m <= bp.Pb; ++X) {
-            uint32_t sx = (uint32_t)(p >> (bp.Pb - (X + 1) * m)) & c.mmask;
+            const uint32_t sx = (uint32_t)(p >> (bp.Pb - (X + 1) * m)) & c.mmask;
             ok = (c.rep[X * P + sx] & 0xFFFFu) >= t;
         }
-        uint64_t w = EMIT ? offsets[p] : 0;
+        uint64_t wpos = EMIT ? offsets[p] : 0;
         if (ok) {
             uint64_t v = (r == 0) ? 0ull : ((1ull << r) - 1ull);
             const uint64_t vend = 1ull << R;
+            const uint64_t top = (uint64_t)t << (N - m);
             while (v < vend) {
                 const uint64_t sgm = (p << R) | v;
                 // quick reject: every block's Rep must be >= the top block
                 uint32_t tie = 0;
                 bool pass = true;
                 for (int X = 0; X < ns; ++X) {
-                    uint32_t sx = (uint32_t)(sgm >> (N - (X + 1) * m)) & c.mmask;
-                    uint32_t rv = c.rep[X * P + sx] & 0xFFFFu;
-                    if (rv < t) { pass = false; break; }
+                    const uint32_t sx = (uint32_t)(sgm >> (N - (X + 1) * m)) & c.mmask;
+                    const uint32_t rv = c.rep[X * P + sx] & 0xFFFFu;
+                    if (rv < t) {
+                        pass = false;
+                        break;
+                    }
                     if (rv == t) tie |= 1u << X;
                 }
                 if (pass) {
@@ -455,35 +696,40 @@ __global__ void __launch_bounds__(256) k_basis_enum(DevModel dm, BuildParams bp,
                         const int Y = __builtin_ctz(tie);
                         tie &= tie - 1;
                         const uint32_t sy = (uint32_t)(sgm >> (N - (Y + 1) * m)) & c.mmask;
-                        for (uint32_t k = c.sym_off[Y * (P + 1) + sy]; k < c.sym_off[Y * (P + 1) + sy + 1]; ++k) {
-                            const uint32_t g = c.sym_list[k];
-                            const uint32_t u = c.g_u[g];
-                            const AT *au = c.act + (size_t)u * ns * P;
-                            const uint8_t *sh = c.u_shift + u * ns;
-                            uint64_t img = 0;
-                            for (int X = 0; X < ns; ++X) {
-                                uint32_t sx = (uint32_t)(sgm >> (N - (X + 1) * m)) & c.mmask;
-                                img |= (uint64_t)au[X * P + sx] << sh[X];
+                        const uint32_t off = c.rep[Y * P + sy] >> 16;
+                        const uint32_t n_g = c.sym[off];
+                        for (uint32_t k = 1; k <= n_g; ++k) {
+                            const uint32_t ent = c.sym[off + k];
+                            const uint32_t g = ent & 0xFFFFu;
+                            const uint64_t img = image_below_top(c, (ent >> 16) & 0x7FFFu, ent >> 31, Y, sgm) | top;
+                            if (img < sgm) {
+                                is_rep = false;
+                                break;
                             }
-                            if (c.g_flip[g]) img ^= (c.low_mask | ((uint64_t)c.mmask << (N - m)));
-                            if (img < sgm) { is_rep = false; break; }
                             if (img == sgm) {
                                 ++nstab;
-                                if (!dm.trivial_irrep &&
-                                    (fabs(c.chi[2 * g] - 1.0) > 1e-9 || fabs(c.chi[2 * g + 1]) > 1e-9))
-                                    compat = false;
+                                if (!dm.trivial_irrep) {
+                                    double cr, ci;
+                                    if (dm.is_complex) {
+                                        cr = c.chi[2 * g];
+                                        ci = c.chi[2 * g + 1];
+                                    } else {
+                                        cr = c.chi[g];
+                                        ci = 0.0;
+                                    }
+                                    if (fabs(cr - 1.0) > 1e-9 || fabs(ci) > 1e-9) compat = false;
+                                }
                             }
                         }
                     }
                     if (is_rep && compat) {
                         if (EMIT) {
-                            // index of nstab among the divisors of |G|
                             int lo = 0, hi = dm.n_div - 1;
                             while (lo < hi) {
-                                int mid = (lo + hi) >> 1;
-                                if (div_val[mid] < nstab) lo = mid + 1; else hi = mid;
+                                const int mid = (lo + hi) >> 1;
+                                if (c.div_val[mid] < nstab) lo = mid + 1; else hi = mid;
                             }
-                            out[w++] = ((uint64_t)lo << kNormShift) | sgm;
+                            out[wpos++] = ((uint64_t)lo << kNormShift) | sgm;
                         }
                         ++cnt;
                     }
@@ -512,16 +758,15 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tile(const TIn *in, uint6
     uint64_t run = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        uint64_t idx = base + k;
-        uint64_t v = idx < n ? (uint64_t)in[idx] : 0ull;
+        const uint64_t idx = base + k;
+        const uint64_t v = idx < n ? (uint64_t)in[idx] : 0ull;
         loc[k] = run;
         run += v;
     }
     sh[threadIdx.x] = run;
     __syncthreads();
-    // Hillis-Steele inclusive scan of the per-thread totals
     for (int o = 1; o < kScanThreads; o <<= 1) {
-        uint64_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0ull;
+        const uint64_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0ull;
         __syncthreads();
         sh[threadIdx.x] += add;
         __syncthreads();
@@ -529,7 +774,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tile(const TIn *in, uint6
     const uint64_t excl = sh[threadIdx.x] - run;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        uint64_t idx = base + k;
+        const uint64_t idx = base + k;
         if (idx < n) out[idx] = loc[k] + excl;
     }
     if (threadIdx.x == kScanThreads - 1) tile_sums[blockIdx.x] = sh[threadIdx.x];
@@ -555,10 +800,39 @@ __global__ void k_limits(const uint64_t *states, int64_t D, const uint16_t *top_
         const uint64_t lb = ((uint64_t)top_vals[rank] << (N - m)) | (low << key_shift);
         int64_t lo = 0, hi = D;
         while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
+            const int64_t mid = (lo + hi) >> 1;
             if ((states[mid] & kStateMask) < lb) lo = mid + 1; else hi = mid;
         }
         limits[k] = (uint32_t)lo;
+    }
+}
+
+// slot table: clear, then insert every representative by linear probing
+__global__ void k_slots_clear(uint64_t *slots_u64, uint64_t n_u64)
+{
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_u64; k += (uint64_t)gridDim.x * blockDim.x)
+        slots_u64[k] = kEmpty;
+}
+
+__global__ void k_slots_insert(const uint64_t *states, int64_t D, char *slots, int log2n, int slot_bytes,
+                               uint32_t *slot_of, unsigned int *overflow)
+{
+    const uint64_t smask = (1ull << log2n) - 1ull;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < D; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = states[j];
+        uint64_t sl = slot_of_state(key & kStateMask, log2n);
+        bool done = false;
+        for (uint64_t probe = 0; probe <= smask; ++probe) {
+            unsigned long long *kp = (unsigned long long *)(slots + sl * (uint64_t)slot_bytes);
+            const unsigned long long old = atomicCAS(kp, (unsigned long long)kEmpty, (unsigned long long)key);
+            if (old == kEmpty) {
+                slot_of[j] = (uint32_t)sl;
+                done = true;
+                break;
+            }
+            sl = (sl + 1) & smask;
+        }
+        if (!done) atomicAdd(overflow, 1u);
     }
 }
 
@@ -586,20 +860,17 @@ __device__ double block_sum(double v, double *sh)
     return t;   // valid in thread 0
 }
 
-// partial sums of |v|^2 (n doubles = D or 2D)
-__global__ void __launch_bounds__(kVecThreads) k_norm2_partial(const double *v, int64_t n, double *partials,
-                                                                  const LzState *lz)
+__global__ void __launch_bounds__(kVecThreads) k_norm2_partial(const double *v, int64_t n, double *partials)
 {
     __shared__ double sh[kVecThreads / kWave];
-    if (lz && lz->done) return;
     double a = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         a += v[i] * v[i];
-    double t = block_sum(a, sh);
+    const double t = block_sum(a, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// v_out = v_in * (1 / sqrt(sum of partials)), recomputing the sum per block
+// v_out = v_in / sqrt(sum of partials), the sum recomputed in fixed order per block
 __global__ void __launch_bounds__(kVecThreads) k_scale_by_norm(const double *vin, double *vout, int64_t n,
                                                                   const double *partials, int np)
 {
@@ -614,7 +885,6 @@ __global__ void __launch_bounds__(kVecThreads) k_scale_by_norm(const double *vin
         vout[i] = vin[i] * inv;
 }
 
-// alpha_j = sum of partials; record it
 __global__ void k_lz_alpha(LzState *lz, const double *partials, int np, double *alpha_hist)
 {
     if (lz->done) return;
@@ -626,7 +896,8 @@ __global__ void k_lz_alpha(LzState *lz, const double *partials, int np, double *
     }
 }
 
-// w -= alpha v ; partial |w|^2 ; psi += s_j v (second pass)
+// w -= alpha v ; partial |w|^2 ; psi += s_j v (second pass).  n counts
+// doubles: complex vectors are handled by the same loop since alpha is real.
 __global__ void __launch_bounds__(kVecThreads) k_lz_update(double *w, const double *v, int64_t n, double *partials,
                                                               const LzState *lz, double *psi, const double *svec)
 {
@@ -642,38 +913,10 @@ __global__ void __launch_bounds__(kVecThreads) k_lz_update(double *w, const doub
         acc += wi * wi;
         if (psi) psi[i] += sj * vi;
     }
-    double t = block_sum(acc, sh);
+    const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// complex variant: alpha is real, w and v interleaved
-__global__ void __launch_bounds__(kVecThreads) k_lz_update_c(double *w, const double *v, int64_t nc, double *partials,
-                                                                const LzState *lz, double *psi, const double *svec)
-{
-    __shared__ double sh[kVecThreads / kWave];
-    if (lz->done) return;
-    const double a = lz->alpha_cur;
-    const double sj = psi ? svec[lz->j] : 0.0;
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += (int64_t)gridDim.x * blockDim.x) {
-        double2 vi = ((const double2 *)v)[i];
-        double2 wi = ((double2 *)w)[i];
-        wi.x -= a * vi.x;
-        wi.y -= a * vi.y;
-        ((double2 *)w)[i] = wi;
-        acc += wi.x * wi.x + wi.y * wi.y;
-        if (psi) {
-            double2 pv = ((double2 *)psi)[i];
-            pv.x += sj * vi.x;
-            pv.y += sj * vi.y;
-            ((double2 *)psi)[i] = pv;
-        }
-    }
-    double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
-}
-
-// beta_j = sqrt(sum of partials); breakdown test; advance j
 __global__ void k_lz_beta(LzState *lz, const double *partials, int np, double *beta_hist, int n_steps, double tol)
 {
     if (lz->done) return;
@@ -689,8 +932,8 @@ __global__ void k_lz_beta(LzState *lz, const double *partials, int np, double *b
     }
 }
 
-// v_new = w / beta_j (written over the oldest vector); beta_prev <- beta_j
-__global__ void __launch_bounds__(kVecThreads) k_lz_normalize(const double *w, double *vnew, int64_t n, LzState *lz)
+// v_new = w / beta_j, written over the oldest vector
+__global__ void __launch_bounds__(kVecThreads) k_lz_normalize(const double *w, double *vnew, int64_t n, const LzState *lz)
 {
     if (lz->done) return;
     const double inv = 1.0 / lz->beta_cur;
@@ -711,7 +954,7 @@ __global__ void k_lz_shift_beta(LzState *lz)
 int device_alloc(ed_basis *b, void **p, size_t bytes)
 {
     *p = nullptr;
-    if (bytes == 0) bytes = 8;
+    if (bytes == 0) bytes = 16;
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -730,71 +973,153 @@ static int num_cus()
     return n;
 }
 
-// All tables in one blob whose layout equals the LDS image (the action table
-// sits at the end so that it can be left out of LDS).
-static int upload_tables(ed_basis *b, hipStream_t st, bool act_u8)
+static int lds_limit()
+{
+    int dev = 0, v = 65536;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        v = 65536;
+    return v;
+}
+
+// Pack every table into one blob laid out as the LDS image.
+static int upload_tables(ed_basis *b, hipStream_t st)
 {
     const Tables &t = b->t;
     DevModel &dm = b->dm;
-    auto align16 = [](uint32_t v) { return (v + 15u) & ~15u; };
     const uint32_t P = t.P;
-    std::vector<char> blob;
-    auto put = [&](const void *src, size_t bytes) -> uint32_t {
-        uint32_t off = align16((uint32_t)blob.size());
-        blob.resize(off + bytes);
-        if (bytes) memcpy(blob.data() + off, src, bytes);
-        return off;
-    };
-    dm.lds_rep = put(t.rep.data(), t.rep.size() * 4);
-    dm.lds_sym_off = put(t.sym_off.data(), t.sym_off.size() * 4);
-    dm.lds_sym_list = put(t.sym_list.data(), t.sym_list.size() * 2);
-    std::vector<uint8_t> ush((size_t)t.nu * t.ns);
-    for (size_t k = 0; k < ush.size(); ++k) ush[k] = (uint8_t)(t.N - (t.u_tgt[k] + 1) * t.m);
-    dm.lds_u_shift = put(ush.data(), ush.size());
-    dm.lds_g_u = put(t.g_u.data(), t.g_u.size() * 2);
-    dm.lds_g_flip = put(t.flip.data(), t.flip.size());
-    dm.lds_chi = put(b->chi_host.data(), b->chi_host.size() * 8);
+    const int m = t.m, ns = t.ns;
+    // Sym lists with a count header; rep entries carry the list offset; each
+    // entry carries g, its distinct-permutation index and its flip bit
+    if (t.nu > 0x7FFF) return set_error(ED_ERR_UNSUPPORTED, "%d distinct permutations exceed 32767", t.nu);
+    std::vector<uint32_t> sym;
+    std::vector<uint32_t> rep((size_t)ns * P);
+    for (int X = 0; X < ns; ++X) {
+        for (uint32_t s = 0; s < P; ++s) {
+            const uint32_t k0 = t.sym_off[(size_t)X * (P + 1) + s], k1 = t.sym_off[(size_t)X * (P + 1) + s + 1];
+            const size_t off = sym.size();
+            if (off > 0xFFFFu) return set_error(ED_ERR_UNSUPPORTED, "Sym_X lists exceed 65535 entries");
+            sym.push_back(k1 - k0);
+            for (uint32_t k = k0; k < k1; ++k) {
+                const uint32_t g = t.sym_list[k];
+                sym.push_back(g | ((uint32_t)t.g_u[g] << 16) | (t.flip[g] ? 0x80000000u : 0u));
+            }
+            rep[(size_t)X * P + s] = (t.rep[(size_t)X * P + s] & 0xFFFFu) | ((uint32_t)off << 16);
+        }
+    }
+    std::vector<uint8_t> shift((size_t)t.nu * ns);
+    for (size_t k = 0; k < shift.size(); ++k) shift[k] = (uint8_t)(t.N - (t.u_tgt[k] + 1) * m);
+    std::vector<double> chi;
+    if (dm.is_complex) {
+        chi = b->chi_host;
+    } else {
+        chi.resize(t.ng);
+        for (int g = 0; g < t.ng; ++g) chi[g] = b->chi_host[2 * g];
+    }
     std::vector<double> dv;
     for (uint32_t d : b->divs) dv.push_back(std::sqrt((double)d));
     for (uint32_t d : b->divs) dv.push_back(1.0 / std::sqrt((double)d));
     std::vector<uint32_t> dvals(b->divs.begin(), b->divs.end());
-    dm.lds_div = put(dv.data(), dv.size() * 8);
-    put(dvals.data(), dvals.size() * 4);   // div_val right after the sqrt tables (same 16B alignment chain)
-    // bonds: masks and J/2 are written per call; reserve space
     std::vector<BondLds> bz((size_t)std::max(t.nb, 1));
     for (int k = 0; k < t.nb; ++k) {
-        int p = t.bonds[2 * k], q = t.bonds[2 * k + 1];
+        const int p = t.bonds[2 * k], q = t.bonds[2 * k + 1];
         bz[k].mask = (1ull << (t.N - 1 - p)) | (1ull << (t.N - 1 - q));
         bz[k].jhalf = 0.0;
     }
-    dm.lds_bonds = put(bz.data(), bz.size() * sizeof(BondLds));
-    const uint32_t small_end = align16((uint32_t)blob.size());
-    // action table
-    std::vector<uint8_t> act8;
-    if (act_u8) {
-        act8.resize(t.act.size());
-        for (size_t k = 0; k < t.act.size(); ++k) act8[k] = (uint8_t)t.act[k];
-        dm.lds_act = put(act8.data(), act8.size());
+    // rank of every top-block value, staged only for the Limits index
+    std::vector<uint16_t> rank(b->db.index_mode == IDX_LIMITS ? P : 1, 0);
+    if (b->db.index_mode == IDX_LIMITS)
+        for (size_t r = 0; r < t.top_vals.size(); ++r) rank[t.top_vals[r]] = (uint16_t)r;
+
+    const int lmax = lds_limit();
+    const uint32_t budget = (uint32_t)(lmax - 8192);
+    auto layout = [&](int cb, int esz, std::vector<char> *blob) -> uint32_t {
+        const int nc = (m + cb - 1) / cb;
+        size_t pos = 0;
+        auto put = [&](const void *src, size_t bytes) -> uint32_t {
+            pos = (pos + 15) & ~(size_t)15;
+            const uint32_t off = (uint32_t)pos;
+            if (blob) {
+                blob->resize(pos + bytes);
+                if (bytes && src) memcpy(blob->data() + pos, src, bytes);
+            }
+            pos += bytes;
+            return off;
+        };
+        dm.off_rep = put(rep.data(), rep.size() * 4);
+        dm.off_sym = put(sym.data(), sym.size() * 4);
+        dm.off_shift = put(shift.data(), shift.size());
+        dm.off_chi = put(chi.data(), chi.size() * 8);
+        dm.off_div = put(dv.data(), dv.size() * 8);
+        dm.off_divval = put(dvals.data(), dvals.size() * 4);
+        dm.off_bonds = put(bz.data(), bz.size() * sizeof(BondLds));
+        dm.off_rank = put(rank.data(), rank.size() * 2);
+        // chunked action table [nu][ns][nc][2^cb]; wide entries of chunk 0
+        // also carry the target block index
+        const size_t ent = (size_t)t.nu * ns * nc << cb;
+        const int pos_shift = esz == 2 ? 12 : 16;
+        if (blob) {
+            std::vector<char> act(ent * esz, 0);
+            for (int u = 0; u < t.nu; ++u)
+                for (int X = 0; X < ns; ++X)
+                    for (int k = 0; k < nc; ++k) {
+                        const int width = std::min(cb, m - k * cb);
+                        for (uint32_t v = 0; v < (1u << width); ++v) {
+                            uint32_t img = t.act[((size_t)u * ns + X) * P + (v << (k * cb))];
+                            if (esz > 1 && k == 0) img |= (uint32_t)t.u_tgt[(size_t)u * ns + X] << pos_shift;
+                            const size_t idx = ((((size_t)u * ns + X) * nc + k) << cb) | v;
+                            memcpy(&act[idx * esz], &img, esz);   // little endian: low bytes
+                        }
+                    }
+            dm.off_act = put(act.data(), act.size());
+        } else {
+            dm.off_act = put(nullptr, ent * esz);
+        }
+        pos = (pos + 15) & ~(size_t)15;
+        if (blob) blob->resize(pos);
+        return (uint32_t)pos;
+    };
+    // Entry widths that can hold an image: 1 byte (m <= 8, no position),
+    // 2 bytes (m <= 12) or 4 bytes, the wide ones with the block position.
+    // Automatic choice: fewest chunks (fewest lookups per block) that fit the
+    // LDS budget, a wide entry if it fits at that chunk count; for a given
+    // chunk count the narrowest equal split is the smallest table.
+    const int wide = m <= 12 ? 2 : 4;
+    int want_esz = b->tuning.table_entry_bytes;
+    if (want_esz == 1 && m > 8) want_esz = wide;
+    if (want_esz == 2 && m > 12) want_esz = 4;
+    int cb = m, esz = want_esz ? want_esz : wide;
+    if (b->tuning.chunk_bits > 0) {
+        cb = std::min(b->tuning.chunk_bits, m);
+        if (!want_esz && layout(cb, esz, nullptr) > budget && m <= 8) esz = 1;
     } else {
-        dm.lds_act = put(t.act.data(), t.act.size() * 2);
+        bool found = false;
+        for (int nc = 1; nc <= m && !found; ++nc) {
+            cb = (m + nc - 1) / nc;
+            if (want_esz) {
+                esz = want_esz;
+                found = layout(cb, esz, nullptr) <= budget;
+            } else {
+                for (int e : {wide, 1}) {
+                    if (e == 1 && m > 8) continue;
+                    esz = e;
+                    if (layout(cb, esz, nullptr) <= budget) {
+                        found = true;
+                        break;
+                    }
+                }
+            }
+        }
     }
-    const uint32_t full_end = align16((uint32_t)blob.size());
-    blob.resize(full_end);
-    (void)P;
-    // decide LDS placement of the action table; keep 8 KB of the per-block
-    // LDS limit for reductions and the adjoint's per-wave accumulators
-    int dev = 0, lds_max = 65536;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds_max <= 0)
-        lds_max = 65536;
-    const uint32_t lds_cap = (uint32_t)lds_max - 8192u;
-    bool fits = full_end <= std::min<uint32_t>(lds_cap, 56u * 1024u);
-    if (b->tuning.table_lds == 1) fits = full_end <= lds_cap;
-    if (b->tuning.table_lds == 2) fits = false;
-    dm.act_in_lds = fits ? 1 : 0;
-    dm.lds_total = fits ? full_end : small_end;
-    if (small_end > lds_cap)
-        return set_error(ED_ERR_UNSUPPORTED, "lookup tables (%u bytes) exceed the LDS budget (%u)", small_end, lds_cap);
+    uint32_t total = layout(cb, esz, nullptr);
+    if (total > (uint32_t)(lmax - 8192))
+        return set_error(ED_ERR_UNSUPPORTED, "lookup tables need %u bytes of LDS (limit %d)", total, lmax - 8192);
+    dm.act_bytes = esz;
+    std::vector<char> blob;
+    total = layout(cb, esz, &blob);
+    dm.chunk_bits = cb;
+    dm.n_chunks = (m + cb - 1) / cb;
+    dm.lds_total = total;
     void *d = nullptr;
     int rc = device_alloc(b, &d, blob.size());
     if (rc) return rc;
@@ -804,28 +1129,22 @@ static int upload_tables(ed_basis *b, hipStream_t st, bool act_u8)
     return ED_OK;
 }
 
-static inline const char *blob_ptr(const ed_basis *b) { return b->dm.blob; }
-static inline bool act_is_u8(const ed_basis *b) { return b->t.m <= 8; }
-
 // bonds' J/2 live inside the blob; rewrite them when J changes
 static int upload_couplings(const ed_basis *bc, const double *J, hipStream_t st, double *jsum_quarter)
 {
     ed_basis *b = const_cast<ed_basis *>(bc);
     const Tables &t = b->t;
-    double js0 = 0.0;
-    for (int k = 0; k < t.nb; ++k) js0 += J[k];
-    *jsum_quarter = 0.25 * js0;
+    double js = 0.0;
+    for (int k = 0; k < t.nb; ++k) js += J[k];
+    *jsum_quarter = 0.25 * js;
     if ((int)b->J_cache.size() == t.nb && std::equal(b->J_cache.begin(), b->J_cache.end(), J)) return ED_OK;
     std::vector<BondLds> bz((size_t)std::max(t.nb, 1));
-    double js = 0.0;
     for (int k = 0; k < t.nb; ++k) {
-        int p = t.bonds[2 * k], q = t.bonds[2 * k + 1];
+        const int p = t.bonds[2 * k], q = t.bonds[2 * k + 1];
         bz[k].mask = (1ull << (t.N - 1 - p)) | (1ull << (t.N - 1 - q));
         bz[k].jhalf = 0.5 * J[k];
-        js += J[k];
     }
-    *jsum_quarter = 0.25 * js;
-    char *dst = (char *)blob_ptr(b) + b->dm.lds_bonds;
+    char *dst = (char *)b->dm.blob + b->dm.off_bonds;
     HIP_TRY(hipMemcpyAsync(dst, bz.data(), (size_t)t.nb * sizeof(BondLds), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     b->J_cache.assign(J, J + t.nb);
@@ -840,7 +1159,7 @@ int check_couplings(const ed_basis *b, const double *J)
     std::vector<int> seen(t.nb, 0);
     for (int k = 0; k < t.nb; ++k) {
         if (!std::isfinite(J[k])) return set_error(ED_ERR_ARG, "J[%d] is not finite", k);
-        int o = t.bond_orbit[k];
+        const int o = t.bond_orbit[k];
         if (!seen[o]) {
             seen[o] = 1;
             first[o] = J[k];
@@ -855,25 +1174,25 @@ int check_couplings(const ed_basis *b, const double *J)
 }
 
 template <typename Kern>
-static int launch_cfg(const ed_basis *b, Kern kern, int lds_extra, int *grid, int *threads, size_t *lds)
+static void launch_cfg(const ed_basis *b, Kern kern, size_t lds, int *grid, int *threads)
 {
-    int th = b->tuning.block_threads > 0 ? b->tuning.block_threads : 256;
+    // one 1024-thread block per CU when the tables take most of the LDS
+    const int th = b->tuning.block_threads > 0 ? b->tuning.block_threads
+                                               : ((int)b->dm.lds_total * 2 > lds_limit() ? 1024 : 512);
     *threads = th;
-    *lds = (size_t)b->dm.lds_total + (size_t)lds_extra;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, th, *lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, th, lds) != hipSuccess || per_cu < 1) per_cu = 1;
     if (b->tuning.blocks_per_cu > 0) per_cu = std::min(per_cu, b->tuning.blocks_per_cu);
     const int64_t need = (b->db.dim + th - 1) / th;
     int64_t g = (int64_t)per_cu * num_cus();
     if (g > need) g = need;
     if (g < 1) g = 1;
     *grid = (int)g;
-    return ED_OK;
 }
 
 // ---- basis build ---------------------------------------------------------
 
-template <typename AT, bool ACT_LDS>
+template <typename AT>
 static int build_impl(ed_basis *b, hipStream_t st)
 {
     Tables &t = b->t;
@@ -900,22 +1219,20 @@ static int build_impl(ed_basis *b, hipStream_t st)
         (void)hipFree(counts);
         (void)hipFree(offsets);
     };
-    const char *blob = blob_ptr(b);
     const int threads = 256;
     const size_t lds = dm.lds_total;
     int per_cu = 1;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_basis_enum<AT, ACT_LDS, false>, threads, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_basis_enum<AT, false>, threads, lds);
     per_cu = std::max(per_cu, 1);
-    uint64_t grid = std::min<uint64_t>((np + threads - 1) / threads, (uint64_t)per_cu * num_cus() * 8);
-    hipLaunchKernelGGL((k_basis_enum<AT, ACT_LDS, false>), dim3((unsigned)grid), dim3(threads), lds, st, dm, bp, blob,
-                       counts, (const uint64_t *)nullptr, (uint64_t *)nullptr);
+    const uint64_t grid = std::min<uint64_t>((np + threads - 1) / threads, (uint64_t)per_cu * num_cus() * 8);
+    hipLaunchKernelGGL((k_basis_enum<AT, false>), dim3((unsigned)grid), dim3(threads), lds, st, dm, bp, counts,
+                       (const uint64_t *)nullptr, (uint64_t *)nullptr);
     if (hipGetLastError() != hipSuccess) {
         cleanup();
         return set_error(ED_ERR_HIP, "basis count launch failed");
     }
-    // exclusive scan counts -> offsets (multi-level)
     {
-        std::vector<std::pair<uint64_t *, uint64_t>> levels;   // (array, n) to be fixed up
+        std::vector<std::pair<uint64_t *, uint64_t>> levels;
         uint64_t n = np;
         const void *in = counts;
         bool in32 = true;
@@ -923,7 +1240,7 @@ static int build_impl(ed_basis *b, hipStream_t st)
         std::vector<void *> tmp;
         int rc = ED_OK;
         while (true) {
-            uint64_t tiles = (n + kScanTile - 1) / kScanTile;
+            const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
             uint64_t *sums = nullptr;
             if (hipMalloc((void **)&sums, std::max<uint64_t>(tiles, 1) * 8) != hipSuccess) {
                 rc = set_error(ED_ERR_OOM, "scan scratch");
@@ -949,14 +1266,12 @@ static int build_impl(ed_basis *b, hipStream_t st)
             outp = next_out;
             n = tiles;
         }
-        // fix up from the coarsest level down
         for (int lv = (int)levels.size() - 2; rc == ED_OK && lv >= 0; --lv) {
-            uint64_t nn = levels[lv].second;
-            unsigned g = (unsigned)std::min<uint64_t>((nn + 255) / 256, 65536);
+            const uint64_t nn = levels[lv].second;
+            const unsigned g = (unsigned)std::min<uint64_t>((nn + 255) / 256, 65536);
             hipLaunchKernelGGL(k_scan_add, dim3(g), dim3(256), 0, st, levels[lv].first, nn,
                                (const uint64_t *)levels[lv + 1].first);
         }
-        // total = offsets[np-1] + counts[np-1]
         uint64_t last_off = 0;
         uint32_t last_cnt = 0;
         if (rc == ED_OK) {
@@ -975,7 +1290,7 @@ static int build_impl(ed_basis *b, hipStream_t st)
     const int64_t D = b->db.dim;
     if (D >= (int64_t)0xFFFFFFFFll) {
         cleanup();
-        return set_error(ED_ERR_UNSUPPORTED, "sector dimension %lld needs 64-bit Limits", (long long)D);
+        return set_error(ED_ERR_UNSUPPORTED, "sector dimension %lld exceeds 32-bit indices", (long long)D);
     }
     void *states = nullptr;
     int rc = device_alloc(b, &states, (size_t)std::max<int64_t>(D, 1) * 8);
@@ -983,136 +1298,195 @@ static int build_impl(ed_basis *b, hipStream_t st)
         cleanup();
         return rc;
     }
-    hipLaunchKernelGGL((k_basis_enum<AT, ACT_LDS, true>), dim3((unsigned)grid), dim3(threads), lds, st, dm, bp, blob,
+    hipLaunchKernelGGL((k_basis_enum<AT, true>), dim3((unsigned)grid), dim3(threads), lds, st, dm, bp,
                        (uint32_t *)nullptr, (const uint64_t *)offsets, (uint64_t *)states);
     if (hipGetLastError() != hipSuccess) {
         cleanup();
         return set_error(ED_ERR_HIP, "basis emit launch failed");
     }
-    // Limits over (top-block rank, next q bits)
-    const int n_top = (int)t.top_vals.size();
-    int q = b->tuning.limits_bits;
-    const int avail = N - m;
-    if (q <= 0) {
-        // about 4 states per key, at most 2^28 keys
-        double target = std::max(1.0, (double)D / 4.0 / std::max(1, n_top));
-        q = (int)std::ceil(std::log2(target));
-        q = std::max(q, 0);
-        while (q > 0 && ((uint64_t)n_top << q) > (1ull << 28)) --q;
-    }
-    q = std::min(q, avail);
-    b->db.key_bits = q;
-    b->db.key_shift = N - m - q;
-    b->db.n_keys = (int64_t)n_top << q;
-    void *tv = nullptr, *lim = nullptr;
-    rc = device_alloc(b, &tv, t.top_vals.size() * 2);
-    if (!rc) rc = device_alloc(b, &lim, ((size_t)b->db.n_keys + 1) * 4);
-    if (rc) {
-        cleanup();
-        return rc;
-    }
-    HIP_TRY(hipMemcpyAsync(tv, t.top_vals.data(), t.top_vals.size() * 2, hipMemcpyHostToDevice, st));
-    {
-        unsigned g = (unsigned)std::min<uint64_t>(((uint64_t)b->db.n_keys + 256) / 256, 1u << 20);
-        hipLaunchKernelGGL(k_limits, dim3(g), dim3(256), 0, st, (const uint64_t *)states, D, (const uint16_t *)tv, N, m, q,
-                           b->db.key_shift, (uint64_t)b->db.n_keys, (uint32_t *)lim);
-    }
     if (hipStreamSynchronize(st) != hipSuccess) {
         cleanup();
-        return set_error(ED_ERR_HIP, "basis build failed: %s", hipGetErrorString(hipGetLastError()));
+        return set_error(ED_ERR_HIP, "basis emit failed: %s", hipGetErrorString(hipGetLastError()));
     }
     cleanup();
     b->db.states = (const uint64_t *)states;
-    b->db.limits = (const uint32_t *)lim;
+
+    if (b->db.index_mode == IDX_LIMITS) {
+        // Limits over (top-block rank, next q bits)
+        const int n_top = (int)t.top_vals.size();
+        int q = b->tuning.limits_bits;
+        const int avail = N - m;
+        if (q <= 0) {
+            const double target = std::max(1.0, (double)D / 4.0 / std::max(1, n_top));
+            q = std::max((int)std::ceil(std::log2(target)), 0);
+            while (q > 0 && ((uint64_t)n_top << q) > (1ull << 28)) --q;
+        }
+        q = std::min(q, avail);
+        b->db.key_bits = q;
+        b->db.key_shift = N - m - q;
+        b->db.n_keys = (int64_t)n_top << q;
+        void *tv = nullptr, *lim = nullptr;
+        rc = device_alloc(b, &tv, t.top_vals.size() * 2);
+        if (!rc) rc = device_alloc(b, &lim, ((size_t)b->db.n_keys + 1) * 4);
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(tv, t.top_vals.data(), t.top_vals.size() * 2, hipMemcpyHostToDevice, st));
+        const unsigned g = (unsigned)std::min<uint64_t>(((uint64_t)b->db.n_keys + 256) / 256, 1u << 20);
+        hipLaunchKernelGGL(k_limits, dim3(g), dim3(256), 0, st, (const uint64_t *)states, D, (const uint16_t *)tv, N, m,
+                           q, b->db.key_shift, (uint64_t)b->db.n_keys, (uint32_t *)lim);
+        b->db.limits = (const uint32_t *)lim;
+    } else {
+        // slot table: power-of-two slots, load factor at most hash_load_pct
+        const int slot_bytes = dm.is_complex ? 32 : 16;
+        const int pct = b->tuning.hash_load_pct > 0 ? std::min(std::max(b->tuning.hash_load_pct, 10), 90) : 30;
+        const double need = std::max(2.0, (double)D * 100.0 / pct);
+        const int lg = std::max((int)std::ceil(std::log2(need)), 1);
+        if (lg > 32) return set_error(ED_ERR_UNSUPPORTED, "slot table exceeds 32-bit slot indices");
+        b->db.slot_log2 = lg;
+        b->n_slots = (int64_t)1 << lg;
+        void *slots = nullptr, *slot_of = nullptr, *ovf = nullptr;
+        const size_t sbytes = (size_t)slot_bytes << lg;
+        rc = device_alloc(b, &slots, sbytes);
+        if (!rc) rc = device_alloc(b, &slot_of, (size_t)std::max<int64_t>(D, 1) * 4);
+        if (!rc) rc = device_alloc(b, &ovf, 16);
+        if (rc) return rc;
+        HIP_TRY(hipMemsetAsync(ovf, 0, 16, st));
+        const uint64_t nu64 = sbytes / 8;
+        hipLaunchKernelGGL(k_slots_clear, dim3((unsigned)std::min<uint64_t>((nu64 + 255) / 256, 1u << 20)), dim3(256), 0,
+                           st, (uint64_t *)slots, nu64);
+        if (D > 0)
+            hipLaunchKernelGGL(k_slots_insert, dim3((unsigned)std::min<int64_t>((D + 255) / 256, 1 << 20)), dim3(256), 0,
+                               st, (const uint64_t *)states, D, (char *)slots, lg, slot_bytes, (uint32_t *)slot_of,
+                               (unsigned int *)ovf);
+        unsigned int h_ovf = 0;
+        HIP_TRY(hipMemcpyAsync(&h_ovf, ovf, 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (h_ovf) return set_error(ED_ERR_HIP, "slot table insertion failed for %u states", h_ovf);
+        b->db.slots = (char *)slots;
+        b->db.slot_of = (const uint32_t *)slot_of;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return set_error(ED_ERR_HIP, "basis build failed: %s", hipGetErrorString(hipGetLastError()));
     return ED_OK;
 }
 
 int launch_basis_build(ed_basis *b, void *stream)
 {
     hipStream_t st = (hipStream_t)stream;
-    const bool u8 = act_is_u8(b);
-    int rc = upload_tables(b, st, u8);
+    b->db.index_mode = b->tuning.index_mode == 1 ? IDX_LIMITS : IDX_HASH;
+    int rc = upload_tables(b, st);
     if (rc) return rc;
-    if (u8) return b->dm.act_in_lds ? build_impl<uint8_t, true>(b, st) : build_impl<uint8_t, false>(b, st);
-    return b->dm.act_in_lds ? build_impl<uint16_t, true>(b, st) : build_impl<uint16_t, false>(b, st);
+    if (b->dm.act_bytes == 1) return build_impl<uint8_t>(b, st);
+    if (b->dm.act_bytes == 2) return build_impl<uint16_t>(b, st);
+    return build_impl<uint32_t>(b, st);
 }
 
 // ---- H.v -----------------------------------------------------------------
 
-template <bool CPLX, typename AT, bool ACT_LDS, int MODE>
+static int pack_input(const ed_basis *b, const void *x, hipStream_t st)
+{
+    if (b->db.index_mode != IDX_HASH || b->db.dim == 0) return ED_OK;
+    const int64_t D = b->db.dim;
+    const unsigned g = (unsigned)std::min<int64_t>((D + 255) / 256, (int64_t)num_cus() * 16);
+    if (b->dm.is_complex)
+        hipLaunchKernelGGL(k_pack_cplx, dim3(g), dim3(256), 0, st, (const double2 *)x, b->db.slot_of, b->db.slots, D);
+    else
+        hipLaunchKernelGGL(k_pack_real, dim3(g), dim3(256), 0, st, (const double *)x, b->db.slot_of, b->db.slots, D);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(ED_ERR_HIP, "pack launch failed: %s", hipGetErrorString(e));
+    return ED_OK;
+}
+
+template <bool CPLX, typename AT, int INDEX, int MODE, int NS>
 static int apply_impl(const ed_basis *b, const void *x, void *y, const void *vprev, double *partials,
-                      unsigned long long *stats, const LzState *lz, double jsq, hipStream_t st, int *grid_out)
+                      unsigned long long *stats, const LzState *lz, double jsq, hipStream_t st)
 {
     using T = typename Scalar<CPLX>::T;
-    auto kern = k_apply<CPLX, AT, ACT_LDS, MODE>;
+    auto kern = k_apply<CPLX, AT, INDEX, MODE, NS>;
     int grid, threads;
-    size_t lds;
-    launch_cfg(b, kern, 0, &grid, &threads, &lds);
+    size_t lds = b->dm.lds_total;
+    launch_cfg(b, kern, lds, &grid, &threads);
     if (MODE == 2) {
         lds = std::max(lds, (size_t)threads * 8);
         grid = b->grid_blocks;   // fixed grid so the reductions are deterministic
     }
-    if (grid_out) *grid_out = grid;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, b->dm, b->db, blob_ptr(b), (const T *)x, (T *)y,
-                       (const T *)vprev, partials, stats, lz, jsq);
-    hipError_t e = hipGetLastError();
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, b->dm, b->db, (const T *)x, (T *)y, (const T *)vprev,
+                       partials, stats, lz, jsq);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(ED_ERR_HIP, "H.v launch failed: %s", hipGetErrorString(e));
     return ED_OK;
+}
+
+template <int MODE, bool CPLX, typename AT>
+static int apply_ns(const ed_basis *b, const void *x, void *y, const void *vprev, double *partials,
+                    unsigned long long *stats, const LzState *lz, double jsq, hipStream_t st)
+{
+#define ED_NS(K) \
+    case K: return apply_impl<CPLX, AT, IDX_HASH, MODE, K>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    if (MODE != 1) {
+        switch (b->dm.ns) {
+            ED_NS(2) ED_NS(3) ED_NS(4) ED_NS(5) ED_NS(6) ED_NS(8) ED_NS(9) ED_NS(10)
+        default: break;
+        }
+    }
+#undef ED_NS
+    return apply_impl<CPLX, AT, IDX_HASH, MODE, 0>(b, x, y, vprev, partials, stats, lz, jsq, st);
+}
+
+template <int MODE, typename AT>
+static int apply_dispatch_t(const ed_basis *b, const void *x, void *y, const void *vprev, double *partials,
+                            unsigned long long *stats, const LzState *lz, double jsq, hipStream_t st)
+{
+    const bool c = b->dm.is_complex;
+    if (b->db.index_mode == IDX_LIMITS) {
+        if (c) return apply_impl<true, AT, IDX_LIMITS, MODE, 0>(b, x, y, vprev, partials, stats, lz, jsq, st);
+        return apply_impl<false, AT, IDX_LIMITS, MODE, 0>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    }
+    if (c) return apply_ns<MODE, true, AT>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    return apply_ns<MODE, false, AT>(b, x, y, vprev, partials, stats, lz, jsq, st);
 }
 
 template <int MODE>
 static int apply_dispatch(const ed_basis *b, const void *x, void *y, const void *vprev, double *partials,
                           unsigned long long *stats, const LzState *lz, double jsq, hipStream_t st)
 {
-    const bool c = b->dm.is_complex, u8 = act_is_u8(b), l = b->dm.act_in_lds;
-#define ED_CASE(C, A, L)                                                                             \
-    if (c == C && u8 == (sizeof(A) == 1) && l == L)                                                  \
-        return apply_impl<C, A, L, MODE>(b, x, y, vprev, partials, stats, lz, jsq, st, nullptr);
-    ED_CASE(false, uint8_t, true)
-    ED_CASE(false, uint8_t, false)
-    ED_CASE(false, uint16_t, true)
-    ED_CASE(false, uint16_t, false)
-    ED_CASE(true, uint8_t, true)
-    ED_CASE(true, uint8_t, false)
-    ED_CASE(true, uint16_t, true)
-    ED_CASE(true, uint16_t, false)
-#undef ED_CASE
-    return set_error(ED_ERR_ARG, "no kernel variant");
+    if (b->dm.act_bytes == 1) return apply_dispatch_t<MODE, uint8_t>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    if (b->dm.act_bytes == 2) return apply_dispatch_t<MODE, uint16_t>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    return apply_dispatch_t<MODE, uint32_t>(b, x, y, vprev, partials, stats, lz, jsq, st);
 }
 
 int launch_apply(const ed_basis *b, const double *J, const void *x, void *y, void *stream, int stats_mode,
                  unsigned long long *stats_dev)
 {
     hipStream_t st = (hipStream_t)stream;
+    if (stats_mode) {
+        if (b->db.dim == 0) return ED_OK;
+        return apply_dispatch<1>(b, nullptr, nullptr, nullptr, nullptr, stats_dev, nullptr, 0.0, st);
+    }
     int rc = check_couplings(b, J);
     if (rc) return rc;
     double jsq = 0.0;
-    if (!stats_mode) {
-        rc = upload_couplings(b, J, st, &jsq);
-        if (rc) return rc;
-    }
+    rc = upload_couplings(b, J, st, &jsq);
+    if (rc) return rc;
     if (b->db.dim == 0) return ED_OK;
-    if (stats_mode) return apply_dispatch<1>(b, x, y, nullptr, nullptr, stats_dev, nullptr, 0.0, st);
+    rc = pack_input(b, x, st);
+    if (rc) return rc;
     return apply_dispatch<0>(b, x, y, nullptr, nullptr, nullptr, nullptr, jsq, st);
 }
 
 // ---- adjoint ---------------------------------------------------------------
 
-template <bool CPLX, typename AT, bool ACT_LDS>
+template <bool CPLX, typename AT, int INDEX>
 static int backward_impl(const ed_basis *b, const void *x, const void *gy, double *gJ_host, hipStream_t st)
 {
     using T = typename Scalar<CPLX>::T;
-    auto kern = k_backward_J<CPLX, AT, ACT_LDS>;
+    auto kern = k_backward_J<CPLX, AT, INDEX>;
     const int nb = b->t.nb;
-    int grid, threads;
-    size_t lds;
-    const int threads_req = 256;
+    const int threads = 256;
+    const size_t lds = (size_t)b->dm.lds_total + (size_t)(threads / kWave) * nb * 8;
     int per_cu = 1;
-    lds = (size_t)b->dm.lds_total + (size_t)(threads_req / kWave) * nb * 8;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads_req, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
     per_cu = std::max(per_cu, 1);
-    threads = threads_req;
-    grid = (int)std::min<int64_t>((b->db.dim + threads - 1) / threads, (int64_t)per_cu * num_cus());
+    int grid = (int)std::min<int64_t>((b->db.dim + threads - 1) / threads, (int64_t)per_cu * num_cus());
     grid = std::max(grid, 1);
     double *partials = nullptr, *out = nullptr;
     if (hipMalloc((void **)&partials, (size_t)grid * nb * 8) != hipSuccess ||
@@ -1121,8 +1495,7 @@ static int backward_impl(const ed_basis *b, const void *x, const void *gy, doubl
         if (partials) (void)hipFree(partials);
         return set_error(ED_ERR_OOM, "adjoint partials");
     }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, b->dm, b->db, blob_ptr(b), (const T *)x, (const T *)gy,
-                       partials);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, b->dm, b->db, (const T *)x, (const T *)gy, partials);
     hipLaunchKernelGGL(k_sum_partials_cols, dim3((nb + 255) / 256), dim3(256), 0, st, (const double *)partials, grid, nb,
                        out);
     hipError_t e = hipMemcpyAsync(gJ_host, out, (size_t)nb * 8, hipMemcpyDeviceToHost, st);
@@ -1145,22 +1518,46 @@ int launch_backward_J(const ed_basis *b, const double *J, const void *x, const v
         for (int k = 0; k < b->t.nb; ++k) gJ_host[k] = 0.0;
         return ED_OK;
     }
-    const bool c = b->dm.is_complex, u8 = act_is_u8(b), l = b->dm.act_in_lds;
-#define ED_CASE(C, A, L) \
-    if (c == C && u8 == (sizeof(A) == 1) && l == L) return backward_impl<C, A, L>(b, x, gy, gJ_host, st);
-    ED_CASE(false, uint8_t, true)
-    ED_CASE(false, uint8_t, false)
-    ED_CASE(false, uint16_t, true)
-    ED_CASE(false, uint16_t, false)
-    ED_CASE(true, uint8_t, true)
-    ED_CASE(true, uint8_t, false)
-    ED_CASE(true, uint16_t, true)
-    ED_CASE(true, uint16_t, false)
+    rc = pack_input(b, x, st);
+    if (rc) return rc;
+    const bool c = b->dm.is_complex;
+    const int ix = b->db.index_mode, w = b->dm.act_bytes;
+#define ED_CASE(C, A, I) \
+    if (c == C && w == (int)sizeof(A) && ix == I) return backward_impl<C, A, I>(b, x, gy, gJ_host, st);
+    ED_CASE(false, uint8_t, IDX_HASH)
+    ED_CASE(false, uint16_t, IDX_HASH)
+    ED_CASE(false, uint32_t, IDX_HASH)
+    ED_CASE(true, uint8_t, IDX_HASH)
+    ED_CASE(true, uint16_t, IDX_HASH)
+    ED_CASE(true, uint32_t, IDX_HASH)
+    ED_CASE(false, uint8_t, IDX_LIMITS)
+    ED_CASE(false, uint16_t, IDX_LIMITS)
+    ED_CASE(false, uint32_t, IDX_LIMITS)
+    ED_CASE(true, uint8_t, IDX_LIMITS)
+    ED_CASE(true, uint16_t, IDX_LIMITS)
+    ED_CASE(true, uint32_t, IDX_LIMITS)
 #undef ED_CASE
     return set_error(ED_ERR_ARG, "no kernel variant");
 }
 
 // ---- Lanczos ---------------------------------------------------------------
+
+void free_lanczos_workspace(ed_basis *b)
+{
+    auto &W = b->lzw;
+    for (auto &p : W.vec) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    }
+    for (double **p : {&W.partials, &W.ahist, &W.bhist, &W.svec}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    if (W.state) (void)hipFree(W.state);
+    W.state = nullptr;
+    W.cap_steps = 0;
+    W.cap_partials = 0;
+}
 
 int run_lanczos(const ed_basis *bc, const double *J, const void *v0, int n_steps, double *alpha, double *beta,
                 int *n_done, void *psi0, void *stream)
@@ -1177,43 +1574,41 @@ int run_lanczos(const ed_basis *bc, const double *J, const void *v0, int n_steps
     if (D == 0 || n_steps <= 0) return ED_OK;
     const bool cplx = b->dm.is_complex;
     const int64_t nd = cplx ? 2 * D : D;   // doubles per vector
-    // fixed launch geometry -> deterministic reductions, identical passes
     {
         int grid, threads;
-        size_t lds;
-        launch_cfg(b, k_apply<false, uint8_t, true, 2>, 0, &grid, &threads, &lds);
-        b->grid_blocks = grid;
+        launch_cfg(b, k_apply<false, uint8_t, IDX_HASH, 2, 0>, b->dm.lds_total, &grid, &threads);
+        b->grid_blocks = grid;   // fixed launch geometry -> deterministic reductions
     }
     const int vgrid = (int)std::min<int64_t>((nd + kVecThreads - 1) / kVecThreads, (int64_t)num_cus() * 8);
     const int np_apply = b->grid_blocks;
-    double *A = nullptr, *B = nullptr, *C = nullptr, *partials = nullptr, *ahist = nullptr, *bhist = nullptr,
-           *svec = nullptr;
-    LzState *lz = nullptr;
-    auto freeall = [&]() {
-        for (void *p : {(void *)A, (void *)B, (void *)C, (void *)partials, (void *)ahist, (void *)bhist, (void *)svec,
-                        (void *)lz})
-            if (p) (void)hipFree(p);
-    };
     const size_t vb = (size_t)nd * 8;
-    if (hipMalloc((void **)&A, vb) != hipSuccess || hipMalloc((void **)&B, vb) != hipSuccess ||
-        hipMalloc((void **)&C, vb) != hipSuccess ||
-        hipMalloc((void **)&partials, (size_t)std::max(np_apply, vgrid) * 8) != hipSuccess ||
-        hipMalloc((void **)&ahist, (size_t)n_steps * 8) != hipSuccess ||
-        hipMalloc((void **)&bhist, (size_t)n_steps * 8) != hipSuccess ||
-        hipMalloc((void **)&svec, (size_t)n_steps * 8) != hipSuccess || hipMalloc((void **)&lz, sizeof(LzState)) != hipSuccess) {
-        (void)hipGetLastError();
-        freeall();
-        return set_error(ED_ERR_OOM, "Lanczos vectors (3 x %zu bytes)", vb);
+    auto &W = b->lzw;
+    const size_t npart = (size_t)std::max(np_apply, vgrid);
+    if (!W.vec[0] || W.cap_steps < n_steps || W.cap_partials < npart) {
+        free_lanczos_workspace(b);
+        bool ok = true;
+        for (int k = 0; k < 3; ++k) ok = ok && hipMalloc((void **)&W.vec[k], vb) == hipSuccess;
+        ok = ok && hipMalloc((void **)&W.partials, npart * 8) == hipSuccess;
+        ok = ok && hipMalloc((void **)&W.ahist, (size_t)n_steps * 8) == hipSuccess;
+        ok = ok && hipMalloc((void **)&W.bhist, (size_t)n_steps * 8) == hipSuccess;
+        ok = ok && hipMalloc((void **)&W.svec, (size_t)n_steps * 8) == hipSuccess;
+        ok = ok && hipMalloc(&W.state, sizeof(LzState)) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            free_lanczos_workspace(b);
+            return set_error(ED_ERR_OOM, "Lanczos vectors (3 x %zu bytes)", vb);
+        }
+        W.cap_steps = n_steps;
+        W.cap_partials = npart;
     }
+    double *A = W.vec[0], *B = W.vec[1], *C = W.vec[2], *partials = W.partials, *ahist = W.ahist, *bhist = W.bhist,
+           *svec = W.svec;
+    LzState *lz = (LzState *)W.state;
     std::vector<double> svec_host(n_steps, 0.0);
-    int passes = psi0 ? 2 : 1;
+    const int passes = psi0 ? 2 : 1;
     for (int pass = 0; pass < passes; ++pass) {
         double *psi = pass == 1 ? (double *)psi0 : nullptr;
         LzState init{};
-        init.j = 0;
-        init.done = 0;
-        init.scale = 0.0;
-        init.beta_prev = 0.0;
         HIP_TRY(hipMemcpyAsync(lz, &init, sizeof init, hipMemcpyHostToDevice, st));
         if (psi) {
             HIP_TRY(hipMemsetAsync(psi, 0, vb, st));
@@ -1221,30 +1616,24 @@ int run_lanczos(const ed_basis *bc, const double *J, const void *v0, int n_steps
         }
         // v (B) = v0 / |v0| ; v_prev (A) = 0
         HIP_TRY(hipMemsetAsync(A, 0, vb, st));
-        hipLaunchKernelGGL(k_norm2_partial, dim3(vgrid), dim3(kVecThreads), 0, st, (const double *)v0, nd, partials,
-                           (const LzState *)nullptr);
+        hipLaunchKernelGGL(k_norm2_partial, dim3(vgrid), dim3(kVecThreads), 0, st, (const double *)v0, nd, partials);
         hipLaunchKernelGGL(k_scale_by_norm, dim3(vgrid), dim3(kVecThreads), 0, st, (const double *)v0, B, nd,
                            (const double *)partials, vgrid);
         double *vprev = A, *v = B, *w = C;
         for (int step = 0; step < n_steps; ++step) {
+            rc = pack_input(b, v, st);
+            if (rc) return rc;
             rc = apply_dispatch<2>(b, v, w, vprev, partials, nullptr, lz, jsq, st);
-            if (rc) {
-                freeall();
-                return rc;
-            }
+            if (rc) return rc;
             hipLaunchKernelGGL(k_lz_alpha, dim3(1), dim3(64), 0, st, lz, (const double *)partials, np_apply, ahist);
-            if (cplx)
-                hipLaunchKernelGGL(k_lz_update_c, dim3(vgrid), dim3(kVecThreads), 0, st, w, (const double *)v, D, partials,
-                                   (const LzState *)lz, psi, (const double *)svec);
-            else
-                hipLaunchKernelGGL(k_lz_update, dim3(vgrid), dim3(kVecThreads), 0, st, w, (const double *)v, D, partials,
-                                   (const LzState *)lz, psi, (const double *)svec);
+            hipLaunchKernelGGL(k_lz_update, dim3(vgrid), dim3(kVecThreads), 0, st, w, (const double *)v, nd, partials,
+                               (const LzState *)lz, psi, (const double *)svec);
             hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(64), 0, st, lz, (const double *)partials, vgrid, bhist, n_steps,
                                1e-12);
-            hipLaunchKernelGGL(k_lz_normalize, dim3(vgrid), dim3(kVecThreads), 0, st, (const double *)w, vprev, nd, lz);
+            hipLaunchKernelGGL(k_lz_normalize, dim3(vgrid), dim3(kVecThreads), 0, st, (const double *)w, vprev, nd,
+                               (const LzState *)lz);
             hipLaunchKernelGGL(k_lz_shift_beta, dim3(1), dim3(64), 0, st, lz);
-            // rotate: new v was written over vprev
-            std::swap(vprev, v);
+            std::swap(vprev, v);   // the new v was written over vprev
             if ((step & 15) == 15) {
                 LzState hs;
                 HIP_TRY(hipMemcpyAsync(&hs, lz, sizeof hs, hipMemcpyDeviceToHost, st));
@@ -1261,21 +1650,16 @@ int run_lanczos(const ed_basis *bc, const double *J, const void *v0, int n_steps
         if (pass == 0 && psi0) {
             std::vector<double> ev(hs.j), z(hs.j);
             rc = ed_tridiag_eigh(hs.j, alpha, beta, ev.data(), z.data());
-            if (rc) {
-                freeall();
-                return rc;
-            }
+            if (rc) return rc;
             for (int k = 0; k < hs.j; ++k) svec_host[k] = z[k];
         }
         if (pass == 1) {
-            hipLaunchKernelGGL(k_norm2_partial, dim3(vgrid), dim3(kVecThreads), 0, st, (const double *)psi, nd, partials,
-                               (const LzState *)nullptr);
+            hipLaunchKernelGGL(k_norm2_partial, dim3(vgrid), dim3(kVecThreads), 0, st, (const double *)psi, nd, partials);
             hipLaunchKernelGGL(k_scale_by_norm, dim3(vgrid), dim3(kVecThreads), 0, st, (const double *)psi, psi, nd,
                                (const double *)partials, vgrid);
         }
     }
-    hipError_t e = hipStreamSynchronize(st);
-    freeall();
+    const hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return set_error(ED_ERR_HIP, "Lanczos failed: %s", hipGetErrorString(e));
     return ED_OK;
 }
@@ -1286,9 +1670,9 @@ extern "C" int ed_internal_unpack_states(const ed_basis *b, uint64_t *dev_out, v
 {
     const int64_t D = b->db.dim;
     if (D == 0) return ED_OK;
-    unsigned g = (unsigned)std::min<int64_t>((D + 255) / 256, 65536);
+    const unsigned g = (unsigned)std::min<int64_t>((D + 255) / 256, 65536);
     hipLaunchKernelGGL(ed::k_unpack_states, dim3(g), dim3(256), 0, (hipStream_t)stream, b->db.states, dev_out, D);
-    hipError_t e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ed::set_error(ED_ERR_HIP, "unpack launch: %s", hipGetErrorString(e));
     return ED_OK;
 }
@@ -1301,8 +1685,7 @@ extern "C" int ed_internal_apply_stats(const ed_basis *b, int64_t *kept, int64_t
     unsigned long long h[2] = {0, 0};
     hipError_t e = hipMemcpyAsync(d, h, 16, hipMemcpyHostToDevice, st);
     int rc = ED_OK;
-    if (e == hipSuccess && b->db.dim > 0)
-        rc = ed::apply_dispatch<1>(b, nullptr, nullptr, nullptr, nullptr, d, nullptr, 0.0, st);
+    if (e == hipSuccess && b->db.dim > 0) rc = ed::launch_apply(b, nullptr, nullptr, nullptr, stream, 1, d);
     if (e == hipSuccess && rc == ED_OK) e = hipMemcpyAsync(h, d, 16, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && rc == ED_OK) e = hipStreamSynchronize(st);
     (void)hipFree(d);

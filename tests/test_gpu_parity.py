@@ -54,6 +54,17 @@ def _small_workloads():
 SMALL = _small_workloads()
 
 
+# the paper's Limits + binary-search index, and a narrow action-table split
+LIMITS = {"index_mode": 1}
+VARIANTS = [("square16_k0", LIMITS), ("sq20_j1j2_n5", LIMITS), ("sq10_C4_complex", LIMITS),
+            ("chain14_k3_nup5", LIMITS), ("sq20_j1j2_n5", {"chunk_bits": 2, "block_threads": 256}),
+            ("tri12_A1_even", {"chunk_bits": 3, "hash_load_pct": 85}),
+            ("sq10_C4_complex", {"hash_load_pct": 90, "table_entry_bytes": 4}),
+            ("chain12_odd", {"hash_load_pct": 80, "block_threads": 1024}),
+            ("sq20_j1j2_n10", {"table_entry_bytes": 1}), ("sq20_j1j2_n5", {"table_entry_bytes": 4, "index_mode": 1}),
+            ("tri12_n1_k1", {"table_entry_bytes": 1, "chunk_bits": 5})]
+
+
 @pytest.fixture(scope="module")
 def built():
     ed = _ed()
@@ -63,6 +74,28 @@ def built():
         cache[name] = (w, ed.Basis.from_workload(w))
     yield cache
     for _, (_, b) in cache.items():
+        b.close()
+
+
+@pytest.mark.parametrize("name,tuning", VARIANTS, ids=[f"{n}-{sorted(t.items())}" for n, t in VARIANTS])
+def test_index_and_table_variants(name, tuning):
+    ed = _ed()
+    w = dict(SMALL)[name]
+    b = ed.Basis.from_workload(w, tuning)
+    try:
+        m = bf.Model.from_workload(w)
+        st, stab = bf.basis(m, w.n_up)
+        assert np.array_equal(b.states(), st)
+        x = vec.normal_vector(len(st), seed=4, complex_=w.is_complex)
+        y_ref, kept, dropped = bf.apply(m, st, stab, x)
+        y = b.apply(w.J, torch.as_tensor(x).cuda()).cpu().numpy()
+        assert np.linalg.norm(y - y_ref) <= RTOL * np.linalg.norm(y_ref)
+        assert b.stats() == (len(st), kept, dropped)
+        info = b.info()
+        assert info["index_mode"] == tuning.get("index_mode", 0)
+        if "chunk_bits" in tuning:
+            assert info["chunk_bits"] == tuning["chunk_bits"]
+    finally:
         b.close()
 
 
