@@ -38,6 +38,28 @@ HBM_PEAK_GBS = 8000.0
 BYTES_ROW_REAL, BYTES_TERM_REAL = 25.0, 17.0
 BYTES_ROW_CPLX, BYTES_TERM_CPLX = 41.0, 25.0
 
+# Measured HBM bytes per H.v launch: FETCH_SIZE and WRITE_SIZE runs of
+# rocprofv3, scaled by what the same counters read for a plain device copy of
+# known size (x2.0 and x1.0).  A figure is valid only for the kernel source it
+# was taken on (sha256 of csrc/ed_kernels.hip) and the same configuration;
+# otherwise the roofline reports traffic as null.
+KERNEL_SRC = os.path.join(ROOT, "paper_1804_05028_amd", "csrc", "ed_kernels.hip")
+MEASURED_TRAFFIC = {
+    # (workload, n_sublat, index, chunk_bits): (kernel sha256, fetch bytes, write bytes)
+    ("square40_j1j2", 4, "hash-slot", 5): (
+        "fb3db0fc9adac8c44f56739139a84db89f6f9b8c4e6e6594ac0cc8b55e164095", 5.197e12, 3.447e9),
+}
+
+
+def measured_traffic(key):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(key)
+    if rec is None:
+        return None
+    with open(KERNEL_SRC, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    return rec[1] + rec[2] if digest == rec[0] else None
+
 
 def _workload(name, n_sub):
     from ed_inputs import workloads as wl
@@ -50,6 +72,119 @@ def _workload(name, n_sub):
     if name == "square16":
         return wl.square_4x4(n_sub=n_sub or 4), "Heisenberg square 16 (4x4), 16T, k=0, Sz=0"
     raise SystemExit(f"unknown workload {name}")
+
+
+def _allk_workloads(n_sub):
+    """The 20 inequivalent momentum sectors of the 36-site triangular cluster
+    with translations only: Gamma, the three M points and one momentum of every
+    +-k pair (for real H the sector -k is the complex conjugate of sector k)."""
+    from ed_inputs import lattice as lat
+    from ed_inputs import workloads as wl
+    w0 = wl.triangular_36_momentum(0, n_sub=n_sub or 4)
+    ks = [k for k in range(w0.cluster.n_elems) if k <= lat.conjugate_momentum_index(w0.cluster, k)]
+    return [wl.triangular_36_momentum(k, n_sub=n_sub or 4) for k in ks]
+
+
+def bench_allk(args):
+    """Batched all-sector H.v and Lanczos against one launch per sector."""
+    import torch
+    from paper_1804_05028_amd import ed
+    ws = _allk_workloads(args.n_sub)
+    J = ws[0].J
+    reps = max(args.hv_reps, 1)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    # one launch per sector, sector by sector (each with its own basis and index)
+    per_ms, per_terms = 0.0, 0
+    for w in ws:
+        b = ed.Basis.from_workload(w)
+        n_diag, kept, _ = b.stats()
+        per_terms += n_diag + kept
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(0)
+        x = torch.randn(b.dim, dtype=b.dtype, device="cuda", generator=gen)
+        y = b.empty()
+        b.apply(J, x, out=y)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            b.apply(J, x, out=y)
+        ev1.record()
+        torch.cuda.synchronize()
+        per_ms += ev0.elapsed_time(ev1) / reps
+        print(f"[bench] sector {w.name}: D={b.dim} {ev0.elapsed_time(ev1) / reps:.1f} ms", file=sys.stderr, flush=True)
+        del x, y
+        b.close()
+        torch.cuda.empty_cache()
+
+    # batched: sectors in groups of --batch, search and lookup shared per group
+    groups = [ws[i:i + args.batch] for i in range(0, len(ws), args.batch)]
+    hv_ms, terms, shared_terms, lz_s, lz_steps, build_s, e0 = 0.0, 0, 0, 0.0, 0, 0.0, []
+    info = None
+    for grp in groups:
+        t0 = time.perf_counter()
+        mb = ed.MultiBasis.from_workloads(grp)
+        torch.cuda.synchronize()
+        build_s += time.perf_counter() - t0
+        info = mb.info()
+        t, sh = mb.stats()
+        terms += int(t.sum())
+        shared_terms += sh
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(0)
+        x = torch.randn((mb.dim, mb.K), dtype=torch.complex128, device="cuda", generator=gen)
+        y = mb.empty()
+        mb.apply(J, x, out=y)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            mb.apply(J, x, out=y)
+        ev1.record()
+        torch.cuda.synchronize()
+        hv_ms += ev0.elapsed_time(ev1) / reps
+        del y
+        torch.cuda.empty_cache()
+        if args.warmup > 0:
+            mb.lanczos(J, x, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = mb.lanczos(J, x, args.steps)
+        torch.cuda.synchronize()
+        lz_s += time.perf_counter() - t0
+        lz_steps = max(lz_steps, int(res["n_done"].max()))
+        e0 += [float(e[0]) for e in res["eigenvalues"] if len(e)]
+        del x
+        mb.close()
+        torch.cuda.empty_cache()
+    out = {
+        "metric": METRIC,
+        "value": terms * lz_steps / lz_s,
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": lz_steps,
+        "warmup": args.warmup,
+        "ms_per_step": lz_s * 1e3 / max(lz_steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "triangular36_allk", "n_sectors": len(ws), "batch": args.batch,
+                   "description": "Heisenberg triangular 36 (6,0)x(0,6), 36 T, 20 inequivalent momenta, Sz=0",
+                   "shared_rows": info["dim"] if info else 0, "n_sublat": info["n_sublat"] if info else 0,
+                   "parallelism": "1 GPU"},
+        "batched_hv_ms": hv_ms,
+        "per_sector_hv_ms": per_ms,
+        "batched_speedup": per_ms / hv_ms if hv_ms else None,
+        "terms_per_hv": terms,
+        "per_sector_terms_per_hv": per_terms,
+        "shared_terms_per_hv": shared_terms,
+        "batched_hv_terms_per_s": terms / (hv_ms * 1e-3) if hv_ms else None,
+        "per_sector_hv_terms_per_s": per_terms / (per_ms * 1e-3) if per_ms else None,
+        "basis_build_s": build_s,
+        "lowest_e0": min(e0) if e0 else None,
+    }
+    print(json.dumps(out))
 
 
 def cpu_baseline(w, rows, seed):
@@ -85,6 +220,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="build, then run --hv-reps H.v launches only")
+    ap.add_argument("--batch", type=int, default=10, help="sectors per batched launch (triangular36_allk)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -98,6 +234,8 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs an MI355X GPU")
     torch.cuda.set_device(0)
+    if args.workload == "triangular36_allk":
+        return bench_allk(args)
     w, desc = _workload(args.workload, args.n_sub)
     tuning = dict(limits_bits=args.limits_bits, index_mode=args.index_mode, block_threads=args.block_threads,
                   blocks_per_cu=args.blocks_per_cu, chunk_bits=args.chunk_bits, hash_load_pct=args.hash_load_pct,
@@ -157,8 +295,11 @@ def main():
     br, bt = (BYTES_ROW_CPLX, BYTES_TERM_CPLX) if cplx else (BYTES_ROW_REAL, BYTES_TERM_REAL)
     alg_bytes = D * br + kept * bt
     achieved = alg_bytes / (hv_ms * 1e-3) / 1e9
+    index_name = ["hash-slot", "limits"][info["index_mode"]]
+    traffic = measured_traffic((args.workload, info["n_sublat"], index_name, info["chunk_bits"]))
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                "traffic_gbs": round(traffic / (hv_ms * 1e-3) / 1e9, 1) if traffic else None,
                 "kernel": "k_apply (fused H.v)", "alg_bytes_per_launch": alg_bytes,
                 "launch_ms": round(hv_ms, 3)}
 
@@ -183,7 +324,7 @@ def main():
         "config": {"workload": args.workload, "description": desc, "n_sites": w.cluster.n_sites,
                    "n_up": w.n_up, "group_order": int(w.cluster.n_elems), "dim": D,
                    "terms_per_hv": terms, "offdiag_kept": kept, "offdiag_dropped": dropped,
-                   "n_sublat": info["n_sublat"], "index_mode": ["hash-slot", "limits"][info["index_mode"]],
+                   "n_sublat": info["n_sublat"], "index_mode": index_name,
                    "chunk_bits": info["chunk_bits"], "lds_bytes": info["lds_bytes"], "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -46,6 +46,41 @@ def hashed_amplitudes(states, salt=0, complex_=False):
     return re + 1j * im
 
 
+def _signed(u):
+    return u - (1 << 64) if u >= (1 << 63) else u
+
+
+def _srl(z, k):
+    """Logical right shift of int64 tensors holding uint64 bit patterns."""
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def _splitmix64_torch(z):
+    z = z + _signed(int(_GOLDEN))
+    z = (z ^ _srl(z, 30)) * _signed(int(_M1))
+    z = (z ^ _srl(z, 27)) * _signed(int(_M2))
+    return z ^ _srl(z, 31)
+
+
+def hashed_amplitudes_torch(states, salt=0, complex_=False):
+    """hashed_amplitudes for an int64 torch tensor of states, on its device.
+
+    Integer arithmetic wraps modulo 2^64 as in the NumPy version, so the two
+    agree bit for bit (checked by the tests).
+    """
+    import torch
+    s = states.to(torch.int64)
+    k1 = _signed((int(salt) * int(_M2)) % (1 << 64))
+    re = _splitmix64_torch(s ^ k1)
+    re = _srl(re, 11).to(torch.float64) * (2.0 ** -52) - 1.0
+    if not complex_:
+        return re
+    k2 = _signed((((int(salt) + 1) * int(_M2)) % (1 << 64)) ^ int(_GOLDEN))
+    im = _splitmix64_torch(s ^ k2)
+    im = _srl(im, 11).to(torch.float64) * (2.0 ** -52) - 1.0
+    return torch.complex(re, im)
+
+
 def normal_vector(dim, seed=SEED_VECTOR, complex_=False, normalise=True):
     """N(0,1) entries from numpy's default_rng(seed); complex: independent parts."""
     rng = np.random.default_rng(seed)

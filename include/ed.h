@@ -236,6 +236,79 @@ int ed_apply_H_backward(const ed_basis_t *b, const double *J, const void *x_dev,
                         void *gx_dev, double *gJ_host, void *stream);
 
 /*
+ * Batched sectors.  Several 1-D irreps chi_0 .. chi_{K-1} (K <= 32) of one
+ * group share one set of representatives: the orbit minima of the group,
+ * i.e. the trivial-irrep basis (the representatives are the same for every
+ * irrep, sec. "Symmetry adapted basis states"; an irrep keeps those whose
+ * stabiliser carries its trivial value, the others have zero norm).  Row i of
+ * the shared basis belongs to sector k iff bit k of its mask is set, and
+ * sector k's own basis (ed_build_basis with chi_k) is the subsequence of
+ * shared rows with that bit, in the same order.
+ *
+ * Batched vectors are complex128 [dim][K] (interleaved re, im; sector index
+ * fastest), owned by the caller.  Real sectors use the same layout.
+ */
+typedef struct ed_multi ed_multi_t;
+
+typedef struct {
+    int64_t dim;                /* shared representatives (rows of a batched vector) */
+    int32_t n_sectors;
+    int32_t n_sites, n_up, n_sublat, n_elems, n_bonds;
+    int32_t chunk_bits, table_entry_bytes, lds_bytes;
+    int64_t n_slots;
+    int64_t device_bytes;
+    double build_ms;
+} ed_multi_info_t;
+
+#define ED_LANCZOS_NO_GRAPH 1   /* ed_lanczos_batched: launch the step kernels directly */
+
+/*
+ * Build the shared basis of n_sectors irreps (irreps[k].chi: host
+ * [n_elems][2] each); validates every irrep as ed_validate does.  tuning may
+ * be NULL; the index is always the hash-slot index and action-table entries
+ * are 2 or 4 bytes wide.  Synchronises stream.
+ */
+int ed_build_multi(const ed_lattice_t *lat, const ed_group_t *grp, int32_t n_sectors, const ed_irrep_t *irreps,
+                   int32_t n_up, const ed_tuning_t *tuning, void *stream, ed_multi_t **out);
+void ed_free_multi(ed_multi_t *mb);
+int ed_multi_info(const ed_multi_t *mb, ed_multi_info_t *info);
+/* dims_host[k] = dimension of sector k (rows with bit k set). */
+int ed_multi_sector_dims(const ed_multi_t *mb, int64_t *dims_host);
+/* Shared representatives, ascending -> host [dim] (synchronises). */
+int ed_multi_copy_states(const ed_multi_t *mb, uint64_t *host_out, void *stream);
+/* Sector masks of the shared rows -> host [dim] (synchronises). */
+int ed_multi_copy_masks(const ed_multi_t *mb, uint64_t *host_out, void *stream);
+
+/*
+ * y = H x in every sector at once: y[i][k] is ed_apply_H's row i of sector k
+ * (same formula, character chi_k) when row i belongs to sector k, and 0
+ * otherwise; entries x[j][k] of rows outside sector k are never read.  The
+ * representative search and the index lookup of a term are done once for
+ * all sectors.  x, y: device complex128 [dim][K], distinct.  J as for
+ * ed_apply_H.  Enqueued on stream.
+ */
+int ed_apply_H_batched(const ed_multi_t *mb, const double *J, const void *x_dev, void *y_dev, void *stream);
+
+/*
+ * n_terms[k] = diagonal plus kept off-diagonal terms of sector k's H.v (what
+ * ed_apply_H_stats reports for that sector, n_diag + n_offdiag_kept);
+ * *n_shared_terms = off-diagonal terms of the shared rows, each searched and
+ * looked up once per batched H.v.  Synchronises.
+ */
+int ed_apply_H_batched_stats(const ed_multi_t *mb, int64_t *n_terms, int64_t *n_shared_terms, void *stream);
+
+/*
+ * Lanczos in every sector at once, ed_lanczos's recurrence and stopping rule
+ * applied to each sector separately (v0_dev: device complex128 [dim][K],
+ * entries outside a sector ignored; a sector whose start vector is zero, or
+ * that is empty, reports n_done 0).  alpha_host, beta_host: host
+ * [K][n_steps]; n_done: host [K].  One step's kernels are captured in a HIP
+ * graph and replayed, unless flags has ED_LANCZOS_NO_GRAPH.  Synchronises.
+ */
+int ed_lanczos_batched(const ed_multi_t *mb, const double *J, const void *v0_dev, int32_t n_steps,
+                       double *alpha_host, double *beta_host, int32_t *n_done, int32_t flags, void *stream);
+
+/*
  * Eigenvalues (ascending) of the symmetric tridiagonal matrix with diagonal
  * alpha[0..m) and off-diagonal beta[0..m-1), and optionally the eigenvector
  * of the lowest one (evec0 [m], may be NULL).  Host only.

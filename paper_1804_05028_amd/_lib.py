@@ -66,6 +66,17 @@ class ed_basis_info_t(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double)]
 
 
+class ed_multi_info_t(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int64), ("n_sectors", ctypes.c_int32), ("n_sites", ctypes.c_int32),
+                ("n_up", ctypes.c_int32), ("n_sublat", ctypes.c_int32), ("n_elems", ctypes.c_int32),
+                ("n_bonds", ctypes.c_int32), ("chunk_bits", ctypes.c_int32),
+                ("table_entry_bytes", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
+                ("n_slots", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double)]
+
+
+ED_LANCZOS_NO_GRAPH = 1
+
+
 def _struct_dict(s):
     return {name: getattr(s, name) for name, _ in s._fields_}
 
@@ -94,6 +105,15 @@ PROTOTYPES = {
     "ed_lanczos": (ctypes.c_int, [P, P, P, I32, P, P, P, P, P]),
     "ed_apply_H_backward": (ctypes.c_int, [P, P, P, P, P, P, P]),
     "ed_tridiag_eigh": (ctypes.c_int, [I32, P, P, P, P]),
+    "ed_build_multi": (ctypes.c_int, [P, P, I32, P, I32, P, P, P]),
+    "ed_free_multi": (None, [P]),
+    "ed_multi_info": (ctypes.c_int, [P, P]),
+    "ed_multi_sector_dims": (ctypes.c_int, [P, P]),
+    "ed_multi_copy_states": (ctypes.c_int, [P, P, P]),
+    "ed_multi_copy_masks": (ctypes.c_int, [P, P, P]),
+    "ed_apply_H_batched": (ctypes.c_int, [P, P, P, P, P]),
+    "ed_apply_H_batched_stats": (ctypes.c_int, [P, P, P, P]),
+    "ed_lanczos_batched": (ctypes.c_int, [P, P, P, I32, P, P, P, I32, P]),
 }
 
 _lib = None
@@ -212,15 +232,19 @@ def ed_tables_find_rep(h, states):
     return r, g, c
 
 
+def _tuning(tuning):
+    if tuning is None:
+        return None
+    return ed_tuning_t(int(tuning.get("limits_bits", 0)), int(tuning.get("index_mode", 0)),
+                       int(tuning.get("block_threads", 0)), int(tuning.get("blocks_per_cu", 0)),
+                       int(tuning.get("chunk_bits", 0)), int(tuning.get("hash_load_pct", 0)),
+                       int(tuning.get("table_entry_bytes", 0)))
+
+
 def ed_build_basis(arrays: ModelArrays, n_up, tuning=None, stream=None):
     lat, grp, irr = arrays.refs()
     h = ctypes.c_void_p()
-    tn = None
-    if tuning is not None:
-        tn = ed_tuning_t(int(tuning.get("limits_bits", 0)), int(tuning.get("index_mode", 0)),
-                         int(tuning.get("block_threads", 0)), int(tuning.get("blocks_per_cu", 0)),
-                         int(tuning.get("chunk_bits", 0)), int(tuning.get("hash_load_pct", 0)),
-                         int(tuning.get("table_entry_bytes", 0)))
+    tn = _tuning(tuning)
     check(lib().ed_build_basis(lat, grp, irr, int(n_up), ctypes.byref(tn) if tn is not None else None,
                                stream, ctypes.byref(h)))
     return h
@@ -297,3 +321,68 @@ def ed_tridiag_eigh(alpha, beta, want_vec=True):
     check(lib().ed_tridiag_eigh(m, a.ctypes.data, b.ctypes.data, ev.ctypes.data,
                                 vec.ctypes.data if vec is not None else None))
     return ev[:m], (vec[:m] if vec is not None else None)
+
+
+# ---- batched sectors -----------------------------------------------------------
+
+def ed_build_multi(arrays: ModelArrays, chis, n_up, tuning=None, stream=None):
+    """chis: K character tables (complex [n_elems] or [n_elems][2] each)."""
+    lat, grp, _ = arrays.refs()
+    tabs = []
+    for c in chis:
+        c = np.asarray(c)
+        if np.iscomplexobj(c) or c.ndim == 1:
+            c = np.stack([np.real(c), np.imag(c)], 1)
+        tabs.append(np.ascontiguousarray(c, dtype=np.float64))
+    irreps = (ed_irrep_t * len(tabs))(*[ed_irrep_t(t.ctypes.data) for t in tabs])
+    tn = _tuning(tuning)
+    h = ctypes.c_void_p()
+    check(lib().ed_build_multi(lat, grp, len(tabs), irreps, int(n_up), ctypes.byref(tn) if tn is not None else None,
+                               stream, ctypes.byref(h)))
+    return h
+
+
+def ed_free_multi(h):
+    lib().ed_free_multi(h)
+
+
+def ed_multi_info(h):
+    info = ed_multi_info_t()
+    check(lib().ed_multi_info(h, ctypes.byref(info)))
+    return _struct_dict(info)
+
+
+def ed_multi_sector_dims(h, n_sectors):
+    d = np.zeros(n_sectors, np.int64)
+    check(lib().ed_multi_sector_dims(h, d.ctypes.data))
+    return d
+
+
+def ed_multi_copy_states(h, out, stream=None):
+    return check(lib().ed_multi_copy_states(h, ptr(out), stream))
+
+
+def ed_multi_copy_masks(h, out, stream=None):
+    return check(lib().ed_multi_copy_masks(h, ptr(out), stream))
+
+
+def ed_apply_H_batched(h, J, x_dev, y_dev, stream=None):
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    return check(lib().ed_apply_H_batched(h, J.ctypes.data, ptr(x_dev), ptr(y_dev), stream))
+
+
+def ed_apply_H_batched_stats(h, n_sectors, stream=None):
+    t = np.zeros(n_sectors, np.int64)
+    sh = ctypes.c_int64()
+    check(lib().ed_apply_H_batched_stats(h, t.ctypes.data, ctypes.byref(sh), stream))
+    return t, int(sh.value)
+
+
+def ed_lanczos_batched(h, J, v0_dev, n_steps, n_sectors, flags=0, stream=None):
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    alpha = np.zeros((n_sectors, max(n_steps, 1)), np.float64)
+    beta = np.zeros((n_sectors, max(n_steps, 1)), np.float64)
+    nd = np.zeros(n_sectors, np.int32)
+    check(lib().ed_lanczos_batched(h, J.ctypes.data, ptr(v0_dev), int(n_steps), alpha.ctypes.data,
+                                   beta.ctypes.data, nd.ctypes.data, int(flags), stream))
+    return alpha[:, :n_steps], beta[:, :n_steps], nd

@@ -105,8 +105,8 @@ int ed_tables_find_rep(const ed_tables_t *tt, int64_t n, const uint64_t *states,
     return ED_OK;
 }
 
-int ed_build_basis(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irrep_t *irrep, int32_t n_up,
-                   const ed_tuning_t *tuning, void *stream, ed_basis_t **out)
+static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irrep_t *irrep, int32_t n_up,
+                              const ed_tuning_t *tuning, uint32_t lds_reserve, void *stream, ed_basis_t **out)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!out) return set_error(ED_ERR_ARG, "null output handle");
@@ -124,6 +124,7 @@ int ed_build_basis(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irre
         return rc;
     }
     if (tuning) b->tuning = *tuning;
+    b->lds_reserve = lds_reserve;
     if (b->tuning.block_threads && (b->tuning.block_threads < 64 || b->tuning.block_threads > 1024 ||
                                     b->tuning.block_threads % 64)) {
         delete b;
@@ -169,6 +170,12 @@ int ed_build_basis(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irre
     b->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = b;
     return ED_OK;
+}
+
+int ed_build_basis(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irrep_t *irrep, int32_t n_up,
+                   const ed_tuning_t *tuning, void *stream, ed_basis_t **out)
+{
+    return build_basis_common(lat, grp, irrep, n_up, tuning, 0, stream, out);
 }
 
 void ed_free_basis(ed_basis_t *b)
@@ -313,6 +320,139 @@ static int sturm_count(int m, const double *a, const double *b2, double x)
         if (q < 0.0) ++cnt;
     }
     return cnt;
+}
+
+/* ---- batched sectors ---------------------------------------------------- */
+
+int ed_build_multi(const ed_lattice_t *lat, const ed_group_t *grp, int32_t n_sectors, const ed_irrep_t *irreps,
+                   int32_t n_up, const ed_tuning_t *tuning, void *stream, ed_multi_t **out)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!out) return set_error(ED_ERR_ARG, "null output handle");
+    *out = nullptr;
+    if (!grp || !irreps) return set_error(ED_ERR_ARG, "null argument");
+    if (n_sectors < 1 || n_sectors > 32) return set_error(ED_ERR_UNSUPPORTED, "%d sectors (1..32 supported)", n_sectors);
+    int rc = check_lattice(lat);
+    if (rc) return rc;
+    for (int k = 0; k < n_sectors; ++k) {
+        if (!irreps[k].chi) return set_error(ED_ERR_ARG, "null character table of sector %d", k);
+        rc = ed::validate_model(lat, grp, &irreps[k], n_up, nullptr);
+        if (rc) return rc;
+    }
+    const int ng = grp->n_elems;
+    std::vector<double> ones((size_t)ng * 2, 0.0);
+    for (int g = 0; g < ng; ++g) ones[2 * g] = 1.0;
+    ed_irrep_t trivial{ones.data()};
+    ed_tuning_t tn{};
+    if (tuning) tn = *tuning;
+    tn.index_mode = 0;                          // shared hash-slot index (row index | mask in the value)
+    if (tn.table_entry_bytes == 1) tn.table_entry_bytes = 0;
+    if (tn.table_entry_bytes == 0) tn.table_entry_bytes = lat->n_sublat > 0 && lat->n_sites / lat->n_sublat <= 12 ? 2 : 4;
+    ed_multi *mb = new (std::nothrow) ed_multi();
+    if (!mb) return set_error(ED_ERR_OOM, "host allocation");
+    mb->K = n_sectors;
+    const uint32_t reserve = (uint32_t)(((size_t)ng * n_sectors * 16 + 15) & ~(size_t)15);
+    rc = build_basis_common(lat, grp, &trivial, n_up, &tn, reserve, stream, &mb->base);
+    if (rc) {
+        delete mb;
+        return rc;
+    }
+    mb->chi_host.resize((size_t)n_sectors * ng * 2);
+    for (int k = 0; k < n_sectors; ++k)
+        std::copy(irreps[k].chi, irreps[k].chi + 2 * (size_t)ng, mb->chi_host.begin() + (size_t)k * ng * 2);
+    rc = ed::multi_setup(mb, stream);
+    if (rc) {
+        ed_free_multi(mb);
+        return rc;
+    }
+    mb->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = mb;
+    return ED_OK;
+}
+
+void ed_free_multi(ed_multi_t *mb)
+{
+    if (!mb) return;
+    (void)hipDeviceSynchronize();
+    ed::multi_free_workspace(mb);
+    ed_free_basis(mb->base);
+    delete mb;
+}
+
+int ed_multi_info(const ed_multi_t *mb, ed_multi_info_t *info)
+{
+    if (!mb || !info) return set_error(ED_ERR_ARG, "null argument");
+    memset(info, 0, sizeof *info);
+    const ed_basis *b = mb->base;
+    info->dim = b->db.dim;
+    info->n_sectors = mb->K;
+    info->n_sites = b->t.N;
+    info->n_up = b->n_up;
+    info->n_sublat = b->t.ns;
+    info->n_elems = b->t.ng;
+    info->n_bonds = b->t.nb;
+    info->chunk_bits = b->dm.chunk_bits;
+    info->table_entry_bytes = b->dm.act_bytes;
+    info->lds_bytes = (int32_t)(mb->lds_chi_off + (uint32_t)b->t.ng * mb->K * 16);
+    info->n_slots = b->n_slots;
+    info->device_bytes = b->device_bytes;
+    info->build_ms = mb->build_ms;
+    return ED_OK;
+}
+
+int ed_multi_sector_dims(const ed_multi_t *mb, int64_t *dims_host)
+{
+    if (!mb || !dims_host) return set_error(ED_ERR_ARG, "null argument");
+    for (int k = 0; k < mb->K; ++k) dims_host[k] = mb->dims[k];
+    return ED_OK;
+}
+
+int ed_multi_copy_states(const ed_multi_t *mb, uint64_t *host_out, void *stream)
+{
+    if (!mb) return set_error(ED_ERR_ARG, "null argument");
+    return ed_basis_copy_states(mb->base, host_out, stream);
+}
+
+int ed_multi_copy_masks(const ed_multi_t *mb, uint64_t *host_out, void *stream)
+{
+    if (!mb || (!host_out && mb->base->db.dim > 0)) return set_error(ED_ERR_ARG, "null argument");
+    const int64_t D = mb->base->db.dim;
+    if (D == 0) return ED_OK;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(host_out, mb->masks, (size_t)D * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return set_error(ED_ERR_HIP, "copy masks: %s", hipGetErrorString(e));
+    return ED_OK;
+}
+
+int ed_apply_H_batched(const ed_multi_t *mb, const double *J, const void *x_dev, void *y_dev, void *stream)
+{
+    if (!mb) return set_error(ED_ERR_ARG, "null basis");
+    if (mb->base->db.dim > 0 && (!x_dev || !y_dev)) return set_error(ED_ERR_ARG, "null vector");
+    if (mb->base->db.dim > 0 && x_dev == y_dev) return set_error(ED_ERR_ARG, "x and y must be distinct");
+    return ed::multi_apply(mb, J, x_dev, y_dev, stream);
+}
+
+int ed_apply_H_batched_stats(const ed_multi_t *mb, int64_t *n_terms, int64_t *n_shared_terms, void *stream)
+{
+    if (!mb || !n_terms || !n_shared_terms) return set_error(ED_ERR_ARG, "null argument");
+    return ed::multi_stats(mb, n_terms, n_shared_terms, stream);
+}
+
+int ed_lanczos_batched(const ed_multi_t *mbc, const double *J, const void *v0_dev, int32_t n_steps,
+                       double *alpha_host, double *beta_host, int32_t *n_done, int32_t flags, void *stream)
+{
+    if (!mbc || !n_done || (n_steps > 0 && (!alpha_host || !beta_host)))
+        return set_error(ED_ERR_ARG, "null argument");
+    if (n_steps < 0) return set_error(ED_ERR_ARG, "n_steps < 0");
+    if (mbc->base->db.dim > 0 && !v0_dev) return set_error(ED_ERR_ARG, "null start vector");
+    if (flags & ~ED_LANCZOS_NO_GRAPH) return set_error(ED_ERR_ARG, "unknown flags 0x%x", flags);
+    ed_multi *mb = const_cast<ed_multi *>(mbc);
+    std::vector<int> nd(mb->K, 0);
+    const int rc = ed::multi_lanczos(mb, J, v0_dev, n_steps, alpha_host, beta_host, nd.data(),
+                                     (flags & ED_LANCZOS_NO_GRAPH) ? 0 : 1, stream);
+    for (int k = 0; k < mb->K; ++k) n_done[k] = nd[k];
+    return rc;
 }
 
 int ed_tridiag_eigh(int32_t m, const double *alpha, const double *beta, double *evals, double *evec0)

@@ -121,10 +121,35 @@ struct ed_basis {
     int grid_blocks = 0;
     int64_t n_slots = 0;
     std::vector<double> J_cache;   // couplings currently written into the blob
+    uint32_t lds_reserve = 0;      // LDS bytes kept free for kernels that stage more
     // Lanczos workspace, kept between calls and freed with the handle
     struct {
         double *vec[3] = {nullptr, nullptr, nullptr};
         double *partials = nullptr, *ahist = nullptr, *bhist = nullptr, *svec = nullptr;
+        void *state = nullptr;
+        int cap_steps = 0;
+        size_t cap_partials = 0;
+    } lzw;
+};
+
+// Several sectors (1-D irreps of one group) over one shared set of orbit
+// representatives: the union basis is the trivial-irrep basis, each row
+// carries a mask of the sectors its stabiliser is compatible with, and the
+// slot table's value field holds the row index and that mask.
+struct ed_multi {
+    ed_basis *base = nullptr;      // representatives of every orbit, hash-slot index
+    int K = 0;                     // sectors
+    std::vector<double> chi_host;  // [K][ng][2]
+    uint64_t *masks = nullptr;     // [dim] bit k: compatible with sector k (owned by base)
+    void *chi_dev = nullptr;       // [ng][K] double2 (owned by base)
+    std::vector<int64_t> dims;     // [K]
+    uint32_t lds_chi_off = 0;      // LDS byte offset of the staged character table
+    double build_ms = 0.0;
+    int grid_blocks = 0;
+    // Lanczos workspace, kept between calls
+    struct {
+        void *vec[3] = {nullptr, nullptr, nullptr};
+        double *partials = nullptr, *ahist = nullptr, *bhist = nullptr, *sector = nullptr;
         void *state = nullptr;
         int cap_steps = 0;
         size_t cap_partials = 0;
@@ -140,6 +165,14 @@ int launch_backward_J(const ed_basis *b, const double *J, const void *x, const v
                       void *stream);
 int run_lanczos(const ed_basis *b, const double *J, const void *v0, int n_steps, double *alpha, double *beta,
                 int *n_done, void *psi0, void *stream);
+int check_couplings(const ed_basis *b, const double *J);
+// Batched sectors (ed_multi.hip)
+int multi_setup(ed_multi *mb, void *stream);
+int multi_apply(const ed_multi *mb, const double *J, const void *x, void *y, void *stream);
+int multi_stats(const ed_multi *mb, int64_t *terms, int64_t *shared_terms, void *stream);
+int multi_lanczos(ed_multi *mb, const double *J, const void *v0, int n_steps, double *alpha, double *beta,
+                  int *n_done, int use_graph, void *stream);
+void multi_free_workspace(ed_multi *mb);
 int device_alloc(ed_basis *b, void **p, size_t bytes);
 void free_lanczos_workspace(ed_basis *b);
 const char *last_error();

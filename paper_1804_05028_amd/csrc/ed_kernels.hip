@@ -14,336 +14,9 @@
 //               of every key (top-block rank, next q bits), then binary search.
 //   x, y[D]     double (or double2), ascending-representative order.
 // All lookup tables are staged once per persistent block in LDS.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstring>
-#include <vector>
-
-#include "ed_internal.hpp"
+#include "ed_device.hpp"
 
 namespace ed {
-
-#define HIP_TRY(expr)                                                                             \
-    do {                                                                                          \
-        hipError_t e_ = (expr);                                                                   \
-        if (e_ != hipSuccess) return set_error(ED_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-constexpr int kMaxBondWords = 4;   // up to 256 bonds
-constexpr int kWave = 64;
-constexpr uint64_t kEmpty = ~0ull;  // empty slot key (norm index 255 never occurs)
-
-enum { IDX_HASH = 0, IDX_LIMITS = 1 };
-
-struct BondLds {
-    uint64_t mask;     // both sites of the bond
-    double jhalf;      // J_b / 2
-};
-
-// ---------------------------------------------------------------------------
-// LDS staging
-// ---------------------------------------------------------------------------
-template <typename AT>
-struct Ctx {
-    int N, ns, m, cb, nc;
-    uint32_t mmask, cmask;
-    uint64_t low_mask;           // state bits below the top block
-    const uint32_t *rep;
-    const uint32_t *sym;         // [count, e_1, ...], e = g | u << 16 | flip << 31
-    const AT *act;
-    const uint8_t *shift;
-    const double *chi;           // [ng] real, or [ng][2] complex
-    const double *div_sqrt;
-    const double *div_rsqrt;
-    const uint32_t *div_val;
-    const BondLds *bonds;
-    const uint16_t *rank;
-};
-
-__device__ __forceinline__ void lds_copy(char *dst, const void *src, uint32_t bytes)
-{
-    const uint4 *s = (const uint4 *)src;
-    uint4 *d = (uint4 *)dst;
-    for (uint32_t k = threadIdx.x; k < bytes / 16; k += blockDim.x) d[k] = s[k];
-}
-
-template <typename AT>
-__device__ __forceinline__ Ctx<AT> stage(const DevModel &dm, char *lds)
-{
-    lds_copy(lds, dm.blob, dm.lds_total);
-    __syncthreads();
-    Ctx<AT> c;
-    c.N = dm.N;
-    c.ns = dm.ns;
-    c.m = dm.m;
-    c.cb = dm.chunk_bits;
-    c.nc = dm.n_chunks;
-    c.mmask = dm.P - 1;
-    c.cmask = (1u << dm.chunk_bits) - 1u;
-    c.low_mask = (dm.N - dm.m >= 64) ? ~0ull : ((1ull << (dm.N - dm.m)) - 1ull);
-    c.rep = (const uint32_t *)(lds + dm.off_rep);
-    c.sym = (const uint32_t *)(lds + dm.off_sym);
-    c.act = (const AT *)(lds + dm.off_act);
-    c.shift = (const uint8_t *)(lds + dm.off_shift);
-    c.chi = (const double *)(lds + dm.off_chi);
-    c.div_sqrt = (const double *)(lds + dm.off_div);
-    c.div_rsqrt = c.div_sqrt + dm.n_div;
-    c.div_val = (const uint32_t *)(lds + dm.off_divval);
-    c.bonds = (const BondLds *)(lds + dm.off_bonds);
-    c.rank = (const uint16_t *)(lds + dm.off_rank);
-    return c;
-}
-
-// Action-table entries: uint8 holds the image pattern only (its block
-// position comes from the shift table); uint16 / uint32 entries of chunk 0
-// also carry the target block index above bit 12 / 16, which saves that
-// lookup.
-template <typename AT>
-struct ActTraits {
-    static constexpr bool kPos = sizeof(AT) > 1;
-    static constexpr int kPosShift = sizeof(AT) == 2 ? 12 : 16;
-};
-
-template <typename AT>
-__device__ __forceinline__ uint64_t place_block(const Ctx<AT> &c, uint32_t u, int ns, int X, uint32_t e)
-{
-    if (ActTraits<AT>::kPos) {
-        const uint32_t img = e & ((1u << ActTraits<AT>::kPosShift) - 1u);
-        const int pos = (int)(e >> ActTraits<AT>::kPosShift);
-        return (uint64_t)img << (c.N - (pos + 1) * c.m);
-    }
-    return (uint64_t)e << c.shift[u * ns + X];
-}
-
-// image of block X of s under the permutation u (chunked action table)
-template <typename AT>
-__device__ __forceinline__ uint32_t block_image(const Ctx<AT> &c, uint32_t u, int X, uint32_t sx)
-{
-    const AT *t = c.act + ((size_t)(u * c.ns + X) * c.nc << c.cb);
-    uint32_t v = 0;
-    for (int k = 0; k < c.nc; ++k) v |= t[(k << c.cb) | ((sx >> (k * c.cb)) & c.cmask)];
-    return v;
-}
-
-// all blocks except Y of g s, placed at their target positions, flip applied
-template <typename AT>
-__device__ __forceinline__ uint64_t image_below_top(const Ctx<AT> &c, uint32_t u, uint32_t fl, int Y, uint64_t s)
-{
-    uint64_t v = 0;
-    for (int X = 0; X < c.ns; ++X) {
-        if (X == Y) continue;
-        const uint32_t sx = (uint32_t)(s >> (c.N - (X + 1) * c.m)) & c.mmask;
-        v |= place_block(c, u, c.ns, X, block_image(c, u, X, sx));
-    }
-    if (fl) v ^= c.low_mask;
-    return v;
-}
-
-// ---------------------------------------------------------------------------
-// Alg. "Sublattice coding algorithm for finding the representative":
-//   MinRep = min_X Rep_X(s_X); for every block Y attaining it and every g in
-//   Sym_Y(s_Y), assemble g s from the per-block action table and keep the
-//   strict minimum.  The top block of every candidate is MinRep itself, so
-//   only the other blocks are assembled.
-// ---------------------------------------------------------------------------
-template <typename AT>
-__device__ __forceinline__ uint64_t find_rep(const Ctx<AT> &c, uint64_t s, uint32_t &g_best, uint32_t &min_val)
-{
-    const int N = c.N, m = c.m, ns = c.ns;
-    const uint32_t P = c.mmask + 1;
-    uint32_t minr = 0xFFFFFFFFu, tie = 0;
-    for (int X = 0; X < ns; ++X) {
-        const uint32_t sx = (uint32_t)(s >> (N - (X + 1) * m)) & c.mmask;
-        const uint32_t r = c.rep[X * P + sx] & 0xFFFFu;
-        if (r < minr) {
-            minr = r;
-            tie = 1u << X;
-        } else if (r == minr) {
-            tie |= 1u << X;
-        }
-    }
-    const uint64_t top = (uint64_t)minr << (N - m);
-    uint64_t best = ~0ull;
-    uint32_t bg = 0;
-    while (tie) {
-        const int Y = __builtin_ctz(tie);
-        tie &= tie - 1;
-        const uint32_t sy = (uint32_t)(s >> (N - (Y + 1) * m)) & c.mmask;
-        const uint32_t off = c.rep[Y * P + sy] >> 16;
-        const uint32_t cnt = c.sym[off];
-        for (uint32_t k = 1; k <= cnt; ++k) {
-            const uint32_t ent = c.sym[off + k];
-            const uint32_t g = ent & 0xFFFFu;
-            const uint64_t v = image_below_top(c, (ent >> 16) & 0x7FFFu, ent >> 31, Y, s) | top;
-            if (v < best) {
-                best = v;
-                bg = g;
-            }
-        }
-    }
-    g_best = bg;
-    min_val = minr;
-    return best;
-}
-
-// The same search with the number of sublattices fixed at compile time: the
-// substate blocks stay in registers and the block loops unroll.
-template <typename AT, int NS>
-__device__ __forceinline__ uint64_t find_rep_ns(const Ctx<AT> &c, uint64_t s, uint32_t &g_best)
-{
-    const int N = c.N, m = c.m;
-    const uint32_t P = c.mmask + 1;
-    uint32_t sx[NS];
-    uint32_t minr = 0xFFFFFFFFu;
-#pragma unroll
-    for (int X = 0; X < NS; ++X) {
-        sx[X] = (uint32_t)(s >> (N - (X + 1) * m)) & c.mmask;
-        minr = min(minr, c.rep[X * P + sx[X]] & 0xFFFFu);
-    }
-    uint32_t tie = 0;
-#pragma unroll
-    for (int X = 0; X < NS; ++X) tie |= (uint32_t)((c.rep[X * P + sx[X]] & 0xFFFFu) == minr) << X;
-    const uint64_t top = (uint64_t)minr << (N - m);
-    uint64_t best = ~0ull;
-    uint32_t bg = 0;
-    while (tie) {
-        const int Y = __builtin_ctz(tie);
-        tie &= tie - 1;
-        const uint32_t sy = (uint32_t)(s >> (N - (Y + 1) * m)) & c.mmask;
-        const uint32_t off = c.rep[Y * P + sy] >> 16;
-        const uint32_t cnt = c.sym[off];
-        for (uint32_t k = 1; k <= cnt; ++k) {
-            const uint32_t ent = c.sym[off + k];
-            const uint32_t u = (ent >> 16) & 0x7FFFu;
-            const AT *tu = c.act + ((size_t)u * NS * c.nc << c.cb);
-            uint64_t v = 0;
-#pragma unroll
-            for (int X = 0; X < NS; ++X) {
-                if (X == Y) continue;
-                const AT *t = tu + ((X * c.nc) << c.cb);
-                uint32_t blk = 0;
-                for (int k2 = 0; k2 < c.nc; ++k2) blk |= t[(k2 << c.cb) | ((sx[X] >> (k2 * c.cb)) & c.cmask)];
-                v |= place_block(c, u, NS, X, blk);
-            }
-            if (ent >> 31) v ^= c.low_mask;
-            v |= top;
-            if (v < best) {
-                best = v;
-                bg = ent & 0xFFFFu;
-            }
-        }
-    }
-    g_best = bg;
-    return best;
-}
-
-template <typename AT, int NS>
-__device__ __forceinline__ uint64_t rep_search(const Ctx<AT> &c, uint64_t s, uint32_t &g)
-{
-    if (NS > 0) return find_rep_ns<AT, (NS > 0 ? NS : 1)>(c, s, g);
-    uint32_t mv;
-    return find_rep(c, s, g, mv);
-}
-
-// ---------------------------------------------------------------------------
-// index lookups
-// ---------------------------------------------------------------------------
-// home slot of a state: MurmurHash3's 64-bit finaliser (Appleby), top bits
-__device__ __forceinline__ uint64_t slot_of_state(uint64_t s, int log2n)
-{
-    s ^= s >> 33;
-    s *= 0xff51afd7ed558ccdull;
-    s ^= s >> 33;
-    s *= 0xc4ceb9fe1a85ec53ull;
-    s ^= s >> 33;
-    return log2n ? (s >> (64 - log2n)) : 0ull;
-}
-
-// first 16 bytes of a slot: {key, x} (real) or {key, -} (complex)
-template <bool CPLX>
-__device__ __forceinline__ ulonglong2 load_slot(const char *slots, uint64_t sl)
-{
-    return *(const ulonglong2 *)(slots + (sl << (CPLX ? 5 : 4)));
-}
-
-// Probe from the home slot (whose first 16 bytes are q) until the target or
-// an empty slot; returns 1 and the packed key and amplitude if found.
-template <bool CPLX>
-__device__ __forceinline__ int resolve_slot(const DevBasis &db, ulonglong2 q, uint64_t sl, uint64_t target,
-                                            uint64_t &key, double &vr, double &vi)
-{
-    const uint64_t smask = (1ull << db.slot_log2) - 1ull;
-    while (true) {
-        if (q.x == kEmpty) return 0;
-        if ((q.x & kStateMask) == target) {
-            key = q.x;
-            if (CPLX) {
-                const double2 v = *(const double2 *)(db.slots + (sl << 5) + 16);
-                vr = v.x;
-                vi = v.y;
-            } else {
-                vr = __longlong_as_double((long long)q.y);
-                vi = 0.0;
-            }
-            return 1;
-        }
-        sl = (sl + 1) & smask;
-        q = load_slot<CPLX>(db.slots, sl);
-    }
-}
-
-// the paper's index: Limits(key) -> [begin, end), binary search of the states
-template <typename AT>
-__device__ __forceinline__ int64_t lookup_limits(const Ctx<AT> &c, const DevBasis &db, uint64_t rep, uint32_t min_val,
-                                                 uint64_t &entry)
-{
-    const uint64_t key = ((uint64_t)c.rank[min_val] << db.key_bits) |
-                         ((rep >> db.key_shift) & ((1ull << db.key_bits) - 1ull));
-    uint32_t lo = db.limits[key], hi = db.limits[key + 1];
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        const uint64_t e = db.states[mid];
-        const uint64_t sv = e & kStateMask;
-        if (sv == rep) {
-            entry = e;
-            return (int64_t)mid;
-        }
-        if (sv < rep) lo = mid + 1; else hi = mid;
-    }
-    return -1;
-}
-
-template <bool CPLX>
-struct Scalar;
-template <>
-struct Scalar<false> {
-    using T = double;
-};
-template <>
-struct Scalar<true> {
-    using T = double2;
-};
-
-struct LzState {
-    int j;              // step index
-    int done;           // breakdown or finished
-    double scale;       // running max(|alpha_k|, beta_k)
-    double alpha_cur, beta_cur, beta_prev;
-};
-
-template <bool CPLX, typename AT>
-__device__ __forceinline__ void chi_of(const Ctx<AT> &c, uint32_t g, double &cr, double &ci)
-{
-    if (CPLX) {
-        cr = c.chi[2 * g];
-        ci = c.chi[2 * g + 1];
-    } else {
-        cr = c.chi[g];
-        ci = 0.0;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // H.v, gather form of the parallel matrix-vector multiply:
@@ -353,46 +26,6 @@ __device__ __forceinline__ void chi_of(const Ctx<AT> &c, uint32_t g, double &cr,
 // MODE 0: y = H x.  MODE 1: count kept/dropped terms.  MODE 2: Lanczos
 // w = H v - beta_prev v_prev with per-block <v, w> partial sums.
 // ---------------------------------------------------------------------------
-// antiparallel bonds of a row, one bit per bond, in four named words so that
-// they stay in registers
-struct BondMask {
-    uint64_t w0, w1, w2, w3;
-};
-
-template <typename AT>
-__device__ __forceinline__ uint64_t bond_word(const Ctx<AT> &c, uint64_t s, int w, int nb)
-{
-    uint64_t am = 0;
-    const int bend = min(64, nb - 64 * w);
-    for (int k = 0; k < bend; ++k) {
-        const uint64_t bm = c.bonds[64 * w + k].mask;
-        const uint64_t t = s & bm;
-        am |= (uint64_t)((t != 0) & (t != bm)) << k;
-    }
-    return am;
-}
-
-__device__ __forceinline__ int pop_bond(BondMask &m)
-{
-    if (m.w0) {
-        const int k = __builtin_ctzll(m.w0);
-        m.w0 &= m.w0 - 1;
-        return k;
-    }
-    if (m.w1) {
-        const int k = __builtin_ctzll(m.w1);
-        m.w1 &= m.w1 - 1;
-        return 64 + k;
-    }
-    if (m.w2) {
-        const int k = __builtin_ctzll(m.w2);
-        m.w2 &= m.w2 - 1;
-        return 128 + k;
-    }
-    const int k = __builtin_ctzll(m.w3);
-    m.w3 &= m.w3 - 1;
-    return 192 + k;
-}
 
 template <bool CPLX, typename AT, int INDEX, int MODE, int NS>
 __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const typename Scalar<CPLX>::T *__restrict__ x,
@@ -534,11 +167,6 @@ __global__ void k_pack_cplx(const double2 *x, const uint32_t *slot_of, char *slo
 // are summed across the wave in a fixed tree order, then across waves and
 // blocks in fixed order: the result is deterministic.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 template <bool CPLX, typename AT, int INDEX>
 __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, const typename Scalar<CPLX>::T *__restrict__ x,
@@ -965,22 +593,6 @@ int device_alloc(ed_basis *b, void **p, size_t bytes)
     return ED_OK;
 }
 
-static int num_cus()
-{
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
-    return n;
-}
-
-static int lds_limit()
-{
-    int dev = 0, v = 65536;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
-        v = 65536;
-    return v;
-}
 
 // Pack every table into one blob laid out as the LDS image.
 static int upload_tables(ed_basis *b, hipStream_t st)
@@ -1032,7 +644,7 @@ static int upload_tables(ed_basis *b, hipStream_t st)
         for (size_t r = 0; r < t.top_vals.size(); ++r) rank[t.top_vals[r]] = (uint16_t)r;
 
     const int lmax = lds_limit();
-    const uint32_t budget = (uint32_t)(lmax - 8192);
+    const uint32_t budget = (uint32_t)std::max<int64_t>((int64_t)lmax - 8192 - b->lds_reserve, 0);
     auto layout = [&](int cb, int esz, std::vector<char> *blob) -> uint32_t {
         const int nc = (m + cb - 1) / cb;
         size_t pos = 0;
@@ -1112,8 +724,8 @@ static int upload_tables(ed_basis *b, hipStream_t st)
         }
     }
     uint32_t total = layout(cb, esz, nullptr);
-    if (total > (uint32_t)(lmax - 8192))
-        return set_error(ED_ERR_UNSUPPORTED, "lookup tables need %u bytes of LDS (limit %d)", total, lmax - 8192);
+    if (total > budget)
+        return set_error(ED_ERR_UNSUPPORTED, "lookup tables need %u bytes of LDS (limit %u)", total, budget);
     dm.act_bytes = esz;
     std::vector<char> blob;
     total = layout(cb, esz, &blob);
@@ -1130,7 +742,7 @@ static int upload_tables(ed_basis *b, hipStream_t st)
 }
 
 // bonds' J/2 live inside the blob; rewrite them when J changes
-static int upload_couplings(const ed_basis *bc, const double *J, hipStream_t st, double *jsum_quarter)
+int upload_couplings(const ed_basis *bc, const double *J, hipStream_t st, double *jsum_quarter)
 {
     ed_basis *b = const_cast<ed_basis *>(bc);
     const Tables &t = b->t;

@@ -113,6 +113,85 @@ class Basis:
         return gx, gJ
 
 
+class MultiBasis:
+    """Several 1-D irreps of one group over one shared set of representatives.
+
+    Batched vectors are complex128 tensors of shape [dim, K] (sector index
+    fastest); column k restricted to the rows of sector k is that sector's
+    vector in the order of its own basis.
+    """
+
+    def __init__(self, n_sites, bonds, n_sublat, perm, flip, chis, n_up, tuning=None):
+        _require_gpu()
+        self.arrays = L.ModelArrays(n_sites, bonds, n_sublat, perm, flip, None)
+        self.n_up = int(n_up)
+        self.K = len(chis)
+        self.handle = L.ed_build_multi(self.arrays, chis, n_up, tuning, _stream())
+        self.dim = int(L.ed_multi_info(self.handle)["dim"])
+        self.n_bonds = int(self.arrays.bonds.shape[0])
+
+    @classmethod
+    def from_workloads(cls, ws, tuning=None):
+        """Workloads that share cluster, n_up and couplings, one per sector."""
+        c = ws[0].cluster
+        return cls(c.n_sites, c.bonds, c.n_sublat, c.perm, c.flip, [w.chi for w in ws], ws[0].n_up, tuning)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.ed_free_multi(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        return L.ed_multi_info(self.handle)
+
+    def sector_dims(self):
+        return L.ed_multi_sector_dims(self.handle, self.K)
+
+    def states(self):
+        out = np.empty(self.dim, np.uint64)
+        L.ed_multi_copy_states(self.handle, out, _stream())
+        return out
+
+    def masks(self):
+        out = np.empty(self.dim, np.uint64)
+        L.ed_multi_copy_masks(self.handle, out, _stream())
+        return out
+
+    def empty(self):
+        return torch.empty((self.dim, self.K), dtype=torch.complex128, device="cuda")
+
+    def _check_vec(self, v, name):
+        if not (v.is_cuda and v.is_contiguous() and v.dtype == torch.complex128 and tuple(v.shape) == (self.dim, self.K)):
+            raise ValueError(f"{name} must be a contiguous CUDA complex128 tensor of shape ({self.dim}, {self.K})")
+
+    def apply(self, J, x, out=None):
+        self._check_vec(x, "x")
+        y = self.empty() if out is None else out
+        self._check_vec(y, "out")
+        L.ed_apply_H_batched(self.handle, np.asarray(J, np.float64), x, y, _stream())
+        return y
+
+    def stats(self):
+        """(per-sector terms D_k + kept_k, shared off-diagonal terms)."""
+        return L.ed_apply_H_batched_stats(self.handle, self.K, _stream())
+
+    def lanczos(self, J, v0, n_steps, use_graph=True):
+        self._check_vec(v0, "v0")
+        a, b, nd = L.ed_lanczos_batched(self.handle, np.asarray(J, np.float64), v0, n_steps, self.K,
+                                        0 if use_graph else L.ED_LANCZOS_NO_GRAPH, _stream())
+        evs = []
+        for k in range(self.K):
+            n = int(nd[k])
+            evs.append(L.ed_tridiag_eigh(a[k, :n], b[k, :n], want_vec=False)[0] if n else np.array([]))
+        return dict(alpha=a, beta=b, n_done=nd, eigenvalues=evs)
+
+
 def bond_orbits_from(perm, bonds):
     """Orbit index of every bond under the site permutations."""
     perm = np.asarray(perm)

@@ -1,0 +1,122 @@
+"""Full-size configurations, in the launch configuration the benchmark uses.
+
+At these sizes the oracle cannot build the basis or apply H in full, so the
+checks are the ones it can make one item at a time, plus size-independent
+properties:
+  * the dimension equals the character formula;
+  * the basis is strictly ascending, and sampled rows are representatives
+    with the right stabiliser size;
+  * seeded random representatives found by brute force are in the basis;
+  * sampled rows of y = H x, with x a fixed hash of each representative's
+    bits, match the oracle's row evaluation (1e-12);
+  * Lanczos from two start vectors converges to the same lowest energy.
+"""
+import numpy as np
+import pytest
+import torch
+
+from ed_inputs import lattice as lat
+from ed_inputs import vectors as vec
+from ed_inputs import workloads as wl
+from oracle import bruteforce as bf
+from oracle import dimension as odim
+from oracle import lanczos as olz
+
+pytestmark = pytest.mark.gpu
+
+N_ROWS = 512
+N_REPS = 1000
+
+
+def _ed():
+    from paper_1804_05028_amd import ed
+    return ed
+
+
+def _disorder():
+    w = wl.square_32_disorder(n_sub=4)
+    orbit = lat.bond_orbits(w.cluster)
+    return wl.Workload(w.name, w.cluster, w.chi, w.n_up, lat.orbit_mean(w.J, orbit), w.description)
+
+
+FULL = [
+    ("triangular36", lambda: wl.triangular_36(n_sub=4), 10_524_036),
+    ("square32_disorder", _disorder, 18_784_998),
+    ("triangular36_k1", lambda: wl.triangular_36_momentum(1, n_sub=4), None),
+    ("square40_j1j2", lambda: wl.square_40_j1j2(n_sub=4), 430_909_650),
+]
+
+
+@pytest.mark.parametrize("name,make,dim", FULL, ids=[f[0] for f in FULL])
+def test_fullsize_basis_and_sampled_rows(name, make, dim):
+    ed = _ed()
+    w = make()
+    c = w.cluster
+    print(f"[fullsize] {name}: building", flush=True)
+    b = ed.Basis.from_workload(w)
+    try:
+        D = b.dim
+        assert D == odim.sector_dimension(c.perm, c.flip, w.chi, w.n_up)
+        if dim is not None:
+            assert D == dim
+        m = bf.Model.from_workload(w)
+        st = b.states_device()
+        assert bool((st[1:] > st[:-1]).all())
+        rng = np.random.default_rng(vec.SEED_ROWS)
+        rows = np.sort(rng.choice(D, size=N_ROWS, replace=False))
+        rows_t = torch.as_tensor(rows).cuda()
+        s_rows = st[rows_t].cpu().numpy().astype(np.uint64)
+        # sampled rows are representatives, compatible, with the right |Stab|
+        r, _, stab, comp = bf.rep_many(m, s_rows)
+        assert np.array_equal(r, s_rows) and comp.all()
+        norms = b.norms()
+        assert np.array_equal(norms[rows].astype(np.int64), stab.astype(np.int64))
+        del norms
+        # brute-force representatives are present
+        reps = bf.random_representatives(m, w.n_up, N_REPS, vec.SEED_ROWS + 1)
+        reps_t = torch.as_tensor(reps.astype(np.int64)).cuda()
+        pos = torch.searchsorted(st, reps_t)
+        assert bool((pos < D).all())
+        assert bool((st[pos.clamp(max=D - 1)] == reps_t).all())
+        # sampled rows of H.v against the oracle's row evaluation
+        print(f"[fullsize] {name}: H.v", flush=True)
+        x = vec.hashed_amplitudes_torch(st, salt=1, complex_=b.is_complex)
+        del st
+        y = b.apply(w.J, x)
+        x_rows = x[rows_t].cpu().numpy()
+        assert np.array_equal(x_rows, vec.hashed_amplitudes(s_rows, 1, b.is_complex))
+        y_rows = y[rows_t].cpu().numpy()
+        ref, _, _, rc = bf.rows_apply(m, s_rows, lambda s: vec.hashed_amplitudes(s, 1, b.is_complex))
+        assert rc.all()
+        scale = max(np.abs(ref).max(), 1e-300)
+        err = np.abs(y_rows - ref).max()
+        print(f"[fullsize] {name}: D={D} max row error {err:.3e} (scale {scale:.3e})", flush=True)
+        assert err <= 1e-12 * scale * 10
+        assert np.linalg.norm(y_rows - ref) <= 1e-12 * np.linalg.norm(ref)
+    finally:
+        b.close()
+
+
+LANCZOS = [("triangular36", lambda: wl.triangular_36(n_sub=4)), ("square32_disorder", _disorder)]
+
+
+@pytest.mark.parametrize("name,make", LANCZOS, ids=[f[0] for f in LANCZOS])
+def test_fullsize_lanczos_two_start_vectors(name, make):
+    ed = _ed()
+    w = make()
+    b = ed.Basis.from_workload(w)
+    try:
+        e0 = []
+        for seed in (vec.SEED_VECTOR, 17):
+            g = torch.Generator(device="cuda")
+            g.manual_seed(seed)
+            v0 = torch.randn(b.dim, dtype=torch.float64, device="cuda", generator=g)
+            res = b.lanczos(w.J, v0, 200)
+            conv = olz.converged_ritz(res["alpha"], res["beta"], resid_tol=1e-8)
+            assert len(conv) > 0 and abs(conv[0] - res["eigenvalues"][0]) < 1e-10
+            e0.append(res["eigenvalues"][0])
+        print(f"[fullsize] {name}: E0 = {e0[0]:.12f} / {e0[1]:.12f} (per site {e0[0] / w.cluster.n_sites:.10f})",
+              flush=True)
+        assert abs(e0[0] - e0[1]) <= 1e-9 * abs(e0[0])
+    finally:
+        b.close()
