@@ -61,6 +61,9 @@ def measured_traffic(key):
     return rec[1] + rec[2] if digest == rec[0] else None
 
 
+AUTOTUNE_NSUB = {"square40_j1j2": [4, 5], "triangular36": [3, 4], "square32_disorder": [4, 8], "square16": [2, 4]}
+
+
 def _workload(name, n_sub):
     from ed_inputs import workloads as wl
     if name == "square40_j1j2":
@@ -221,6 +224,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="build, then run --hv-reps H.v launches only")
     ap.add_argument("--batch", type=int, default=10, help="sectors per batched launch (triangular36_allk)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="search sublattice decompositions and launch tunings first, then bench the fastest")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -240,6 +245,15 @@ def main():
     tuning = dict(limits_bits=args.limits_bits, index_mode=args.index_mode, block_threads=args.block_threads,
                   blocks_per_cu=args.blocks_per_cu, chunk_bits=args.chunk_bits, hash_load_pct=args.hash_load_pct,
                   table_entry_bytes=args.table_entry_bytes)
+    tuned = None
+    if args.autotune:
+        from paper_1804_05028_amd import autotune as at
+        best, results = at.autotune(lambda ns: _workload(args.workload, ns)[0], AUTOTUNE_NSUB[args.workload],
+                                    reps=2, log=lambda m: print(m, file=sys.stderr, flush=True))
+        w, desc = _workload(args.workload, best["n_sub"])
+        tuning = dict(best["tuning"])
+        tuned = {"n_sub": best["n_sub"], "tuning": tuning, "hv_ms": best["hv_ms"],
+                 "trials": [(r["n_sub"], r["tuning"], r.get("hv_ms"), r.get("error")) for r in results]}
     print(f"[bench] building basis: {desc}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     basis = ed.Basis.from_workload(w, tuning)
@@ -332,6 +346,8 @@ def main():
         "basis_build_s": build_s,
         "lanczos_e0_after_steps": float(res["eigenvalues"][0]) if len(res["eigenvalues"]) else None,
     }
+    if tuned is not None:
+        out["autotune"] = tuned
     print(json.dumps(out))
     _ = math
 

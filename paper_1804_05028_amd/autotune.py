@@ -1,0 +1,98 @@
+"""Launch-configuration search for the sector H.v on the current GPU.
+
+For each sublattice decomposition offered by the caller and each candidate
+tuning (action-table chunk width and entry width, threads per block, blocks
+per compute unit), build the basis, time a few H.v launches with HIP events
+on the current stream, and keep the fastest.  Configurations the library
+rejects (tables that do not fit in LDS, unsupported entry widths) are
+recorded and skipped.  Every candidate computes the same H.v; only its speed
+differs.
+"""
+from __future__ import annotations
+
+import time
+
+import torch
+
+from . import _lib as L
+from . import ed
+
+
+def default_candidates(sub_bits):
+    """Tunings worth trying for sublattice blocks of sub_bits sites."""
+    out = [{}]   # the library's automatic choice
+    for cb in sorted({(sub_bits + 1) // 2, (sub_bits + 2) // 3}):
+        if 1 <= cb < sub_bits:
+            for th in (512, 1024):
+                out.append({"chunk_bits": cb, "block_threads": th})
+    out.append({"block_threads": 512})
+    if sub_bits <= 8:
+        out.append({"table_entry_bytes": 1})
+    return out
+
+
+def _time_apply(basis, J, reps):
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    x = torch.randn(basis.dim, dtype=basis.dtype, device="cuda", generator=gen)
+    y = basis.empty()
+    basis.apply(J, x, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        basis.apply(J, x, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def autotune(make_workload, n_subs, candidates=None, reps=2, time_limit_s=None, log=None):
+    """Return (best, results).
+
+    make_workload(n_sub) -> workload for one sublattice decomposition;
+    candidates(sub_bits) -> list of tuning dicts (default_candidates if None).
+    best = {"n_sub", "tuning", "hv_ms", "info"}; results lists every trial.
+    """
+    candidates = candidates or default_candidates
+    results = []
+    t_start = time.perf_counter()
+    for ns in n_subs:
+        w = make_workload(ns)
+        sub_bits = w.cluster.n_sites // ns
+        for tn in candidates(sub_bits):
+            if time_limit_s is not None and time.perf_counter() - t_start > time_limit_s:
+                break
+            rec = {"n_sub": ns, "tuning": dict(tn)}
+            try:
+                b = ed.Basis.from_workload(w, tn)
+            except L.EDError as e:
+                rec["error"] = e.name
+                results.append(rec)
+                if log:
+                    log(f"[autotune] n_sub={ns} {tn}: {e.name}")
+                continue
+            try:
+                rec["hv_ms"] = _time_apply(b, w.J, reps)
+                rec["info"] = b.info()
+            finally:
+                b.close()
+                torch.cuda.empty_cache()
+            results.append(rec)
+            if log:
+                log(f"[autotune] n_sub={ns} {tn}: {rec['hv_ms']:.2f} ms")
+    timed = [r for r in results if "hv_ms" in r]
+    if not timed:
+        raise RuntimeError("no candidate configuration could be built")
+    best = min(timed, key=lambda r: r["hv_ms"])
+    return best, results
+
+
+def speedup_table(results):
+    """(n_sub, tuning, ms, ms / best ms) rows, fastest first."""
+    timed = sorted((r for r in results if "hv_ms" in r), key=lambda r: r["hv_ms"])
+    b = timed[0]["hv_ms"]
+    return [(r["n_sub"], r["tuning"], r["hv_ms"], r["hv_ms"] / b) for r in timed]
+
+
+__all__ = ["autotune", "default_candidates", "speedup_table"]

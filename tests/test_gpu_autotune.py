@@ -1,0 +1,33 @@
+"""Launch-configuration search: every candidate computes the same H.v, and the
+chosen configuration reproduces the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from ed_inputs import vectors as vec
+from ed_inputs import workloads as wl
+from oracle import bruteforce as bf
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_picks_a_valid_configuration():
+    from paper_1804_05028_amd import autotune as at
+    from paper_1804_05028_amd import ed
+    best, results = at.autotune(lambda ns: wl.square_20_j1j2(n_sub=ns), [4, 5, 10], reps=2)
+    assert any("hv_ms" in r for r in results)
+    assert best["hv_ms"] == min(r["hv_ms"] for r in results if "hv_ms" in r)
+    tab = at.speedup_table(results)
+    assert tab[0][3] == 1.0 and all(t[3] >= 1.0 for t in tab)
+    w = wl.square_20_j1j2(n_sub=best["n_sub"])
+    b = ed.Basis.from_workload(w, best["tuning"])
+    try:
+        m = bf.Model.from_workload(w)
+        st, stab = bf.basis(m, w.n_up)
+        assert np.array_equal(b.states(), st)
+        x = vec.normal_vector(len(st), seed=9)
+        y = b.apply(w.J, torch.as_tensor(x).cuda()).cpu().numpy()
+        ref, _, _ = bf.apply(m, st, stab, x)
+        assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
+    finally:
+        b.close()
