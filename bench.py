@@ -61,13 +61,16 @@ def measured_traffic(key):
     return rec[1] + rec[2] if digest == rec[0] else None
 
 
-AUTOTUNE_NSUB = {"square40_j1j2": [4, 5], "triangular36": [3, 4], "square32_disorder": [4, 8], "square16": [2, 4]}
+AUTOTUNE_NSUB = {"square40_j1j2": [4, 5], "square40_j1j2j3": [4, 5], "triangular36": [3, 4], "square32_disorder": [4, 8], "square16": [2, 4]}
 
 
 def _workload(name, n_sub):
     from ed_inputs import workloads as wl
     if name == "square40_j1j2":
         return wl.square_40_j1j2(n_sub=n_sub or 4), "J1-J2 square 40 (6,2)x(-2,6), 40T x C4 x flip, Gamma.A.even, Sz=0"
+    if name == "square40_j1j2j3":
+        return (wl.square_40_j1j2j3(n_sub=n_sub or 4),
+                "J1-J2-J3 square 40 (6,2)x(-2,6), J2=0.5 J3=0.25, 40T x C4 x flip, Gamma.A.even, Sz=0")
     if name == "triangular36":
         return wl.triangular_36(n_sub=n_sub or 4), "Heisenberg triangular 36 (6,0)x(0,6), 36T x C6v x flip, Gamma.A1.even, Sz=0"
     if name == "square32_disorder":

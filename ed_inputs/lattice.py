@@ -242,13 +242,18 @@ def chain(n, superlattice_period=None, reflection=False, spin_flip=False, transl
     return build_cluster(f"chain{n}", (n, 0), (0, 1), [(1, 0)], gens, spin_flip, sup)
 
 
-def square(L1, L2, j2=False, rotations=True, mirrors=False, spin_flip=False, superlattice=None, name=None):
-    """Square lattice cluster; nearest (kind 0) and optional diagonal (kind 1) bonds."""
+def square(L1, L2, j2=False, rotations=True, mirrors=False, spin_flip=False, superlattice=None, name=None,
+           j3=False):
+    """Square lattice cluster; nearest (kind 0), optional diagonal (kind 1) and
+    optional third-neighbour (distance 2 along the axes, kind 2) bonds."""
     bv = [(1, 0), (0, 1)]
     kinds = [0, 0]
     if j2:
         bv += [(1, 1), (1, -1)]
         kinds += [1, 1]
+    if j3:
+        bv += [(2, 0), (0, 2)]
+        kinds += [2, 2]
     gens = []
     if rotations:
         gens.append(SQUARE_R90)

@@ -79,6 +79,24 @@ def square_40_j1j2(n_sub=5, j2=0.5):
                     f"J1-J2 (J2/J1={j2}), 40-site tilted square, Sz=0, 40 T x C4 x flip, Gamma.A.even")
 
 
+def square_40_j1j2j3(n_sub=4, j2=0.5, j3=0.25):
+    """40-site tilted square, J1-J2-J3 (the model of the paper's strong-scaling
+    benchmark), 40 T x C4 x flip, Gamma.A.even, Sz=0."""
+    sup = {2: SQ_CHECKER, 4: SQ_2X2, 5: SQ_5, 8: SQ_8, 10: SQ_10}[n_sub]
+    cl = lat.square((6, 2), (-2, 6), j2=True, j3=True, spin_flip=True, superlattice=sup, name="square40j3")
+    J = couplings_by_kind(cl.bond_kind, [1.0, j2, j3])
+    return Workload("square40_j1j2j3", cl, _trivial(cl), 20, J,
+                    f"J1-J2-J3 (J2={j2}, J3={j3}), 40-site tilted square, Sz=0, 40 T x C4 x flip, Gamma.A.even")
+
+
+def square_20_j1j2j3(n_sub=5, j2=0.5, j3=0.25, spin_flip=True):
+    """20-site tilted square (L1=(4,2), L2=(-2,4)), J1-J2-J3; small analogue of the 40-site model."""
+    sup = {1: None, 2: SQ_CHECKER, 4: SQ_2X2, 5: ((2, 1), (-1, 2)), 10: ((1, 3), (-3, 1))}[n_sub]
+    cl = lat.square((4, 2), (-2, 4), j2=True, j3=True, spin_flip=spin_flip, superlattice=sup, name="square20j3")
+    J = couplings_by_kind(cl.bond_kind, [1.0, j2, j3])
+    return Workload("square20_j1j2j3", cl, _trivial(cl), 10, J, "J1-J2-J3, 20-site tilted square")
+
+
 def triangular_36_momentum(momentum_index, n_sub=4):
     """36-site triangular, translations only, momentum sector k (complex if k != -k)."""
     sup = {3: TRI_3, 4: TRI_4, 9: TRI_9}[n_sub]

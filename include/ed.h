@@ -205,6 +205,18 @@ int ed_basis_copy_norms(const ed_basis_t *b, uint16_t *host_out, void *stream);
 int ed_apply_H(const ed_basis_t *b, const double *J, const void *x_dev, void *y_dev, void *stream);
 
 /*
+ * XXZ form of ed_apply_H: each bond contributes the exchange
+ * (Jxy_b / 2)(S+_p S-_q + S-_p S+_q) and the Ising term Jz_b Sz_p Sz_q, both
+ * non-branching two-site terms (sec. "Parallel matrix-vector multiply"; the
+ * matrix element of a flip is Jxy_b / 2 times the same symmetry factors, the
+ * diagonal is sum_b Jz_b (+1/4 parallel, -1/4 antiparallel)).  Jz = NULL
+ * means Jz = Jxy, which is ed_apply_H.  Jxy and Jz: host [n_bonds], each
+ * constant on bond orbits.
+ */
+int ed_apply_H_xxz(const ed_basis_t *b, const double *Jxy, const double *Jz, const void *x_dev, void *y_dev,
+                   void *stream);
+
+/*
  * Term counts of one H.v: diagonal terms (= dim), off-diagonal terms whose
  * target is in the sector, and dropped ones.  Synchronises.
  */
@@ -225,6 +237,10 @@ int ed_apply_H_stats(const ed_basis_t *b, int64_t *n_diag, int64_t *n_offdiag_ke
 int ed_lanczos(const ed_basis_t *b, const double *J, const void *v0_dev, int32_t n_steps,
                double *alpha_host, double *beta_host, int32_t *n_done, void *psi0_dev,
                void *stream);
+
+/* ed_lanczos with the XXZ couplings of ed_apply_H_xxz (Jz = NULL: Jz = Jxy). */
+int ed_lanczos_xxz(const ed_basis_t *b, const double *Jxy, const double *Jz, const void *v0_dev, int32_t n_steps,
+                   double *alpha_host, double *beta_host, int32_t *n_done, void *psi0_dev, void *stream);
 
 /*
  * Adjoint of y = H(J) x: gx = H^dagger gy (= H gy, H is Hermitian) if gx_dev

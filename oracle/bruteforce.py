@@ -52,10 +52,10 @@ def lib():
         L.orc_rep_many.restype = None
         L.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P, i64]
         L.orc_basis.restype = i64
-        L.orc_apply.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P, i64, P, P,
+        L.orc_apply.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, i64, P, P,
                                 P, P, ctypes.c_int, P, P]
         L.orc_apply.restype = None
-        L.orc_row_terms.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P, i64,
+        L.orc_row_terms.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, i64,
                                     P, P, P, P, P, P, P, P]
         L.orc_row_terms.restype = None
         L.orc_max_threads.restype = ctypes.c_int
@@ -67,10 +67,14 @@ def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def _pz(model):
+    return None if model.Jz is None else _p(model.Jz)
+
+
 class Model:
     """Group, irrep and bonds in the flat layout the C oracle reads."""
 
-    def __init__(self, n_sites, perm, flip, chi, bonds=None, J=None):
+    def __init__(self, n_sites, perm, flip, chi, bonds=None, J=None, Jz=None):
         self.n = int(n_sites)
         self.perm = np.ascontiguousarray(perm, dtype=np.int32)
         self.ng = int(self.perm.shape[0])
@@ -80,11 +84,13 @@ class Model:
         self.chi = np.ascontiguousarray(np.stack([chi.real, chi.imag], 1))
         self.bonds = None if bonds is None else np.ascontiguousarray(bonds, dtype=np.int32)
         self.J = None if J is None else np.ascontiguousarray(J, dtype=np.float64)
+        # Ising couplings of the XXZ model; None means Jz = J (Heisenberg)
+        self.Jz = None if Jz is None else np.ascontiguousarray(Jz, dtype=np.float64)
 
     @classmethod
-    def from_workload(cls, w, J=None):
+    def from_workload(cls, w, J=None, Jz=None):
         c = w.cluster
-        return cls(c.n_sites, c.perm, c.flip, w.chi, c.bonds, w.J if J is None else J)
+        return cls(c.n_sites, c.perm, c.flip, w.chi, c.bonds, w.J if J is None else J, Jz)
 
     @property
     def nb(self):
@@ -144,7 +150,7 @@ def apply(model, states, stab, x, nthreads=None):
     if nthreads is None:
         nthreads = 1 if d < 20000 else min(8, L.orc_max_threads())
     L.orc_apply(model.n, model.ng, _p(model.perm), _p(model.flip), _p(model.chi), model.nb,
-                _p(model.bonds), _p(model.J), d, _p(np.ascontiguousarray(states, np.uint64)),
+                _p(model.bonds), _p(model.J), _pz(model), d, _p(np.ascontiguousarray(states, np.uint64)),
                 _p(np.ascontiguousarray(stab, np.int32)), _p(xc), _p(y), int(nthreads),
                 _p(kept), _p(dropped))
     yc = y[:, 0] + 1j * y[:, 1]
@@ -163,7 +169,7 @@ def row_terms(model, rows):
         tgt_stab=np.empty((m, nb), np.int32), tgt_flag=np.empty((m, nb), np.uint8),
         coef=np.empty((m, nb, 2), np.float64))
     L.orc_row_terms(model.n, model.ng, _p(model.perm), _p(model.flip), _p(model.chi), nb,
-                    _p(model.bonds), _p(model.J), m, _p(rows), _p(out["row_stab"]),
+                    _p(model.bonds), _p(model.J), _pz(model), m, _p(rows), _p(out["row_stab"]),
                     _p(out["row_compat"]), _p(out["row_diag"]), _p(out["tgt"]),
                     _p(out["tgt_stab"]), _p(out["tgt_flag"]), _p(out["coef"]))
     out["coef"] = out["coef"][..., 0] + 1j * out["coef"][..., 1]

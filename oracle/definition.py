@@ -46,18 +46,20 @@ def act_all(states, perm_row, flip, n):
     return out
 
 
-def full_hamiltonian(n, states, bonds, J):
-    """Heisenberg H = sum_b J_b S_p.S_q on the fixed-Sz basis, sparse CSR."""
+def full_hamiltonian(n, states, bonds, J, Jz=None):
+    """H = sum_b [J_b/2 (S+_p S-_q + S-_p S+_q) + Jz_b Sz_p Sz_q] on the fixed-Sz
+    basis, sparse CSR; Jz = J (None) is the Heisenberg model S_p.S_q."""
+    Jz = J if Jz is None else Jz
     m = states.shape[0]
     index = {int(v): k for k, v in enumerate(states.tolist())}
     rows, cols, vals = [], [], []
     diag = np.zeros(m)
     one = np.uint64(1)
-    for (p, q), j in zip(bonds, J):
+    for (p, q), j, jz in zip(bonds, J, Jz):
         bp = (states >> np.uint64(n - 1 - p)) & one
         bq = (states >> np.uint64(n - 1 - q)) & one
         same = bp == bq
-        diag += np.where(same, 0.25 * j, -0.25 * j)
+        diag += np.where(same, 0.25 * jz, -0.25 * jz)
         flipped = states ^ (one << np.uint64(n - 1 - p)) ^ (one << np.uint64(n - 1 - q))
         for k in np.nonzero(~same)[0]:
             rows.append(index[int(flipped[k])])
@@ -101,18 +103,20 @@ def symmetrised_columns(n, n_up, perm, flip, chi):
     return np.array(kept, dtype=np.uint64), B, states
 
 
-def sector_matrix(n, n_up, perm, flip, chi, bonds, J):
+def sector_matrix(n, n_up, perm, flip, chi, bonds, J, Jz=None):
     """(representatives, dense B^dagger H B) for one 1-D irrep sector."""
     reps, B, states = symmetrised_columns(n, n_up, np.asarray(perm), np.asarray(flip),
                                           np.asarray(chi, dtype=np.complex128))
-    H = full_hamiltonian(n, states, np.asarray(bonds), np.asarray(J, dtype=np.float64))
+    H = full_hamiltonian(n, states, np.asarray(bonds), np.asarray(J, dtype=np.float64),
+                         None if Jz is None else np.asarray(Jz, dtype=np.float64))
     M = (B.conj().T @ (H @ B)).toarray()
     return reps, M
 
 
-def full_spectrum(n, n_up, bonds, J):
+def full_spectrum(n, n_up, bonds, J, Jz=None):
     states = fixed_sz_states(n, n_up)
-    H = full_hamiltonian(n, states, np.asarray(bonds), np.asarray(J, dtype=np.float64))
+    H = full_hamiltonian(n, states, np.asarray(bonds), np.asarray(J, dtype=np.float64),
+                         None if Jz is None else np.asarray(Jz, dtype=np.float64))
     return np.linalg.eigvalsh(H.toarray())
 
 

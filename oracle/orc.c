@@ -24,6 +24,10 @@
  *     algorithm: every source state sends its terms to the target's index,
  *     found by binary search in the ascending list of representatives;
  *   - the S.S diagonal is +J/4 for parallel and -J/4 for antiparallel pairs.
+ * The Hamiltonian is a sum of non-branching two-site terms (sec. "Parallel
+ * matrix-vector multiply"): per bond an exchange J_b/2 (S+S- + S-S+) and an
+ * Ising part Jz_b Sz Sz; Jz = J (passed as NULL) is the Heisenberg model,
+ * Jz != J the XXZ model.
  */
 #include <math.h>
 #include <stdint.h>
@@ -216,10 +220,11 @@ static int64_t find_state(int64_t dim, const uint64_t *basis, uint64_t s)
  * summed in thread order.
  */
 void orc_apply(int n, int ng, const int32_t *perm, const uint8_t *flip, const double *chi,
-               int nb, const int32_t *bonds, const double *J, int64_t dim, const uint64_t *basis,
-               const int32_t *stab, const double *x, double *y, int nthreads,
+               int nb, const int32_t *bonds, const double *J, const double *Jz, int64_t dim,
+               const uint64_t *basis, const int32_t *stab, const double *x, double *y, int nthreads,
                int64_t *kept, int64_t *dropped)
 {
+    if (!Jz) Jz = J; /* isotropic S.S */
     if (nthreads < 1) nthreads = 1;
     double *acc = (double *)calloc((size_t)nthreads * (size_t)dim * 2, sizeof(double));
     int64_t *kc = (int64_t *)calloc((size_t)nthreads, sizeof(int64_t));
@@ -237,7 +242,7 @@ void orc_apply(int n, int ng, const int32_t *perm, const uint8_t *flip, const do
         for (int b = 0; b < nb; ++b) {
             int p = bonds[2 * b], q = bonds[2 * b + 1];
             int same = get_bit(s, n, p) == get_bit(s, n, q);
-            d += same ? 0.25 * J[b] : -0.25 * J[b];
+            d += same ? 0.25 * Jz[b] : -0.25 * Jz[b];
         }
         yt[2 * j] += d * xr;
         yt[2 * j + 1] += d * xi;
@@ -282,10 +287,11 @@ void orc_apply(int n, int ng, const int32_t *perm, const uint8_t *flip, const do
  * the target: (J_b/2) * chi(g) * sqrt(n_target / n_row).
  */
 void orc_row_terms(int n, int ng, const int32_t *perm, const uint8_t *flip, const double *chi,
-                   int nb, const int32_t *bonds, const double *J, int64_t nrows,
+                   int nb, const int32_t *bonds, const double *J, const double *Jz, int64_t nrows,
                    const uint64_t *rows, int32_t *row_stab, uint8_t *row_compat, double *row_diag,
                    uint64_t *tgt, int32_t *tgt_stab, uint8_t *tgt_flag, double *coef)
 {
+    if (!Jz) Jz = J;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t r = 0; r < nrows; ++r) {
         uint64_t s = rows[r];
@@ -298,7 +304,7 @@ void orc_row_terms(int n, int ng, const int32_t *perm, const uint8_t *flip, cons
             int p = bonds[2 * b], q = bonds[2 * b + 1];
             size_t o = (size_t)r * nb + b;
             int same = get_bit(s, n, p) == get_bit(s, n, q);
-            d += same ? 0.25 * J[b] : -0.25 * J[b];
+            d += same ? 0.25 * Jz[b] : -0.25 * Jz[b];
             tgt[o] = 0;
             tgt_stab[o] = 0;
             tgt_flag[o] = 0;

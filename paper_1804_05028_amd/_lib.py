@@ -105,6 +105,8 @@ PROTOTYPES = {
     "ed_lanczos": (ctypes.c_int, [P, P, P, I32, P, P, P, P, P]),
     "ed_apply_H_backward": (ctypes.c_int, [P, P, P, P, P, P, P]),
     "ed_tridiag_eigh": (ctypes.c_int, [I32, P, P, P, P]),
+    "ed_apply_H_xxz": (ctypes.c_int, [P, P, P, P, P, P]),
+    "ed_lanczos_xxz": (ctypes.c_int, [P, P, P, P, I32, P, P, P, P, P]),
     "ed_build_multi": (ctypes.c_int, [P, P, I32, P, I32, P, P, P]),
     "ed_free_multi": (None, [P]),
     "ed_multi_info": (ctypes.c_int, [P, P]),
@@ -283,6 +285,26 @@ def ed_basis_copy_norms(h, out, stream=None):
 def ed_apply_H(h, J, x_dev, y_dev, stream=None):
     J = np.ascontiguousarray(J, dtype=np.float64)
     return check(lib().ed_apply_H(h, J.ctypes.data, ptr(x_dev), ptr(y_dev), stream))
+
+
+def ed_apply_H_xxz(h, Jxy, Jz, x_dev, y_dev, stream=None):
+    Jxy = np.ascontiguousarray(Jxy, dtype=np.float64)
+    Jz = None if Jz is None else np.ascontiguousarray(Jz, dtype=np.float64)
+    return check(lib().ed_apply_H_xxz(h, Jxy.ctypes.data, None if Jz is None else Jz.ctypes.data, ptr(x_dev),
+                                      ptr(y_dev), stream))
+
+
+def ed_lanczos_xxz(h, Jxy, Jz, v0_dev, n_steps, psi0_dev=None, stream=None):
+    Jxy = np.ascontiguousarray(Jxy, dtype=np.float64)
+    Jz = None if Jz is None else np.ascontiguousarray(Jz, dtype=np.float64)
+    alpha = np.zeros(max(n_steps, 1), np.float64)
+    beta = np.zeros(max(n_steps, 1), np.float64)
+    nd = ctypes.c_int32()
+    check(lib().ed_lanczos_xxz(h, Jxy.ctypes.data, None if Jz is None else Jz.ctypes.data, ptr(v0_dev),
+                               int(n_steps), alpha.ctypes.data, beta.ctypes.data, ctypes.byref(nd),
+                               ptr(psi0_dev), stream))
+    n = nd.value
+    return alpha[:n].copy(), beta[:n].copy(), n
 
 
 def ed_apply_H_stats(h, stream=None):

@@ -254,10 +254,16 @@ int ed_basis_copy_norms(const ed_basis_t *b, uint16_t *host_out, void *stream)
 
 int ed_apply_H(const ed_basis_t *b, const double *J, const void *x_dev, void *y_dev, void *stream)
 {
+    return ed_apply_H_xxz(b, J, nullptr, x_dev, y_dev, stream);
+}
+
+int ed_apply_H_xxz(const ed_basis_t *b, const double *Jxy, const double *Jz, const void *x_dev, void *y_dev,
+                   void *stream)
+{
     if (!b) return set_error(ED_ERR_ARG, "null basis");
     if (b->db.dim > 0 && (!x_dev || !y_dev)) return set_error(ED_ERR_ARG, "null vector");
     if (b->db.dim > 0 && x_dev == y_dev) return set_error(ED_ERR_ARG, "x and y must be distinct");
-    return ed::launch_apply(b, J, x_dev, y_dev, stream, 0, nullptr);
+    return ed::launch_apply(b, Jxy, Jz, x_dev, y_dev, stream, 0, nullptr);
 }
 
 int ed_apply_H_stats(const ed_basis_t *bc, int64_t *n_diag, int64_t *n_kept, int64_t *n_dropped, void *stream)
@@ -278,12 +284,18 @@ int ed_apply_H_stats(const ed_basis_t *bc, int64_t *n_diag, int64_t *n_kept, int
 int ed_lanczos(const ed_basis_t *b, const double *J, const void *v0_dev, int32_t n_steps, double *alpha_host,
                double *beta_host, int32_t *n_done, void *psi0_dev, void *stream)
 {
+    return ed_lanczos_xxz(b, J, nullptr, v0_dev, n_steps, alpha_host, beta_host, n_done, psi0_dev, stream);
+}
+
+int ed_lanczos_xxz(const ed_basis_t *b, const double *Jxy, const double *Jz, const void *v0_dev, int32_t n_steps,
+                   double *alpha_host, double *beta_host, int32_t *n_done, void *psi0_dev, void *stream)
+{
     if (!b || !n_done) return set_error(ED_ERR_ARG, "null argument");
     if (n_steps < 0) return set_error(ED_ERR_ARG, "n_steps < 0");
     if (n_steps > 0 && (!alpha_host || !beta_host)) return set_error(ED_ERR_ARG, "null alpha/beta");
     if (b->db.dim > 0 && !v0_dev) return set_error(ED_ERR_ARG, "null start vector");
     int nd = 0;
-    int rc = ed::run_lanczos(b, J, v0_dev, n_steps, alpha_host, beta_host, &nd, psi0_dev, stream);
+    int rc = ed::run_lanczos(b, Jxy, Jz, v0_dev, n_steps, alpha_host, beta_host, &nd, psi0_dev, stream);
     *n_done = nd;
     return rc;
 }
@@ -295,7 +307,7 @@ int ed_apply_H_backward(const ed_basis_t *b, const double *J, const void *x_dev,
     if (b->db.dim > 0 && !gy_dev) return set_error(ED_ERR_ARG, "null gy");
     if (gx_dev) {
         if (gx_dev == gy_dev) return set_error(ED_ERR_ARG, "gx and gy must be distinct");
-        int rc = ed::launch_apply(b, J, gy_dev, gx_dev, stream, 0, nullptr);
+        int rc = ed::launch_apply(b, J, nullptr, gy_dev, gx_dev, stream, 0, nullptr);
         if (rc) return rc;
     }
     if (gJ_host) {

@@ -28,7 +28,8 @@ enum { IDX_HASH = 0, IDX_LIMITS = 1 };
 
 struct BondLds {
     uint64_t mask;     // both sites of the bond
-    double jhalf;      // J_b / 2
+    double jhalf;      // J_b / 2: exchange amplitude of the flip term
+    double jzhalf;     // Jz_b / 2: an antiparallel bond lowers the diagonal by this
 };
 
 // ---------------------------------------------------------------------------
@@ -404,6 +405,6 @@ inline int lds_limit()
     return v;
 }
 
-int upload_couplings(const ed_basis *bc, const double *J, hipStream_t st, double *jsum_quarter);
+int upload_couplings(const ed_basis *bc, const double *J, const double *Jz, hipStream_t st, double *jsum_quarter);
 
 }  // namespace ed

@@ -159,11 +159,11 @@ struct ed_multi {
 namespace ed {
 // Kernel launchers (ed_kernels.hip)
 int launch_basis_build(ed_basis *b, void *stream);
-int launch_apply(const ed_basis *b, const double *J, const void *x, void *y, void *stream, int stats_mode,
+int launch_apply(const ed_basis *b, const double *J, const double *Jz, const void *x, void *y, void *stream, int stats_mode,
                  unsigned long long *stats_dev);
 int launch_backward_J(const ed_basis *b, const double *J, const void *x, const void *gy, double *gJ_host,
                       void *stream);
-int run_lanczos(const ed_basis *b, const double *J, const void *v0, int n_steps, double *alpha, double *beta,
+int run_lanczos(const ed_basis *b, const double *J, const double *Jz, const void *v0, int n_steps, double *alpha, double *beta,
                 int *n_done, void *psi0, void *stream);
 int check_couplings(const ed_basis *b, const double *J);
 // Batched sectors (ed_multi.hip)

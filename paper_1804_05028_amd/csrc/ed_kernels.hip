@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
         if (INDEX == IDX_HASH) {
             for (int term = 0; term < n_terms; ++term) {
                 const BondLds bd = c.bonds[pop_bond(am)];
-                anti_sum += bd.jhalf;
+                anti_sum += bd.jzhalf;
                 uint32_t g;
                 const uint64_t r = rep_search<AT, NS>(c, s ^ bd.mask, g);
                 const uint64_t sl = slot_of_state(r, db.slot_log2);
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
         } else {
             for (int term = 0; term < n_terms; ++term) {
                 const BondLds bd = c.bonds[pop_bond(am)];
-                anti_sum += bd.jhalf;
+                anti_sum += bd.jzhalf;
                 uint32_t g, mval;
                 const uint64_t r = find_rep(c, s ^ bd.mask, g, mval);
                 uint64_t ej = 0;
@@ -637,6 +637,7 @@ static int upload_tables(ed_basis *b, hipStream_t st)
         const int p = t.bonds[2 * k], q = t.bonds[2 * k + 1];
         bz[k].mask = (1ull << (t.N - 1 - p)) | (1ull << (t.N - 1 - q));
         bz[k].jhalf = 0.0;
+        bz[k].jzhalf = 0.0;
     }
     // rank of every top-block value, staged only for the Limits index
     std::vector<uint16_t> rank(b->db.index_mode == IDX_LIMITS ? P : 1, 0);
@@ -741,25 +742,31 @@ static int upload_tables(ed_basis *b, hipStream_t st)
     return ED_OK;
 }
 
-// bonds' J/2 live inside the blob; rewrite them when J changes
-int upload_couplings(const ed_basis *bc, const double *J, hipStream_t st, double *jsum_quarter)
+// bonds' J/2 and Jz/2 live inside the blob; rewrite them when they change.
+// Jz == nullptr means Jz = J (Heisenberg).  *jsum_quarter = sum_b Jz_b / 4,
+// the diagonal of a row whose bonds are all parallel.
+int upload_couplings(const ed_basis *bc, const double *J, const double *Jz, hipStream_t st, double *jsum_quarter)
 {
     ed_basis *b = const_cast<ed_basis *>(bc);
     const Tables &t = b->t;
+    if (!Jz) Jz = J;
     double js = 0.0;
-    for (int k = 0; k < t.nb; ++k) js += J[k];
+    for (int k = 0; k < t.nb; ++k) js += Jz[k];
     *jsum_quarter = 0.25 * js;
-    if ((int)b->J_cache.size() == t.nb && std::equal(b->J_cache.begin(), b->J_cache.end(), J)) return ED_OK;
+    std::vector<double> key(J, J + t.nb);
+    key.insert(key.end(), Jz, Jz + t.nb);
+    if (b->J_cache == key) return ED_OK;
     std::vector<BondLds> bz((size_t)std::max(t.nb, 1));
     for (int k = 0; k < t.nb; ++k) {
         const int p = t.bonds[2 * k], q = t.bonds[2 * k + 1];
         bz[k].mask = (1ull << (t.N - 1 - p)) | (1ull << (t.N - 1 - q));
         bz[k].jhalf = 0.5 * J[k];
+        bz[k].jzhalf = 0.5 * Jz[k];
     }
     char *dst = (char *)b->dm.blob + b->dm.off_bonds;
     HIP_TRY(hipMemcpyAsync(dst, bz.data(), (size_t)t.nb * sizeof(BondLds), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
-    b->J_cache.assign(J, J + t.nb);
+    b->J_cache = key;
     return ED_OK;
 }
 
@@ -1066,8 +1073,8 @@ static int apply_dispatch(const ed_basis *b, const void *x, void *y, const void 
     return apply_dispatch_t<MODE, uint32_t>(b, x, y, vprev, partials, stats, lz, jsq, st);
 }
 
-int launch_apply(const ed_basis *b, const double *J, const void *x, void *y, void *stream, int stats_mode,
-                 unsigned long long *stats_dev)
+int launch_apply(const ed_basis *b, const double *J, const double *Jz, const void *x, void *y, void *stream,
+                 int stats_mode, unsigned long long *stats_dev)
 {
     hipStream_t st = (hipStream_t)stream;
     if (stats_mode) {
@@ -1075,9 +1082,10 @@ int launch_apply(const ed_basis *b, const double *J, const void *x, void *y, voi
         return apply_dispatch<1>(b, nullptr, nullptr, nullptr, nullptr, stats_dev, nullptr, 0.0, st);
     }
     int rc = check_couplings(b, J);
+    if (!rc && Jz) rc = check_couplings(b, Jz);
     if (rc) return rc;
     double jsq = 0.0;
-    rc = upload_couplings(b, J, st, &jsq);
+    rc = upload_couplings(b, J, Jz, st, &jsq);
     if (rc) return rc;
     if (b->db.dim == 0) return ED_OK;
     rc = pack_input(b, x, st);
@@ -1124,7 +1132,7 @@ int launch_backward_J(const ed_basis *b, const double *J, const void *x, const v
     int rc = check_couplings(b, J);
     if (rc) return rc;
     double jsq;
-    rc = upload_couplings(b, J, st, &jsq);
+    rc = upload_couplings(b, J, nullptr, st, &jsq);
     if (rc) return rc;
     if (b->db.dim == 0 || b->t.nb == 0) {
         for (int k = 0; k < b->t.nb; ++k) gJ_host[k] = 0.0;
@@ -1171,15 +1179,16 @@ void free_lanczos_workspace(ed_basis *b)
     W.cap_partials = 0;
 }
 
-int run_lanczos(const ed_basis *bc, const double *J, const void *v0, int n_steps, double *alpha, double *beta,
-                int *n_done, void *psi0, void *stream)
+int run_lanczos(const ed_basis *bc, const double *J, const double *Jz, const void *v0, int n_steps, double *alpha,
+                double *beta, int *n_done, void *psi0, void *stream)
 {
     ed_basis *b = const_cast<ed_basis *>(bc);
     hipStream_t st = (hipStream_t)stream;
     int rc = check_couplings(b, J);
+    if (!rc && Jz) rc = check_couplings(b, Jz);
     if (rc) return rc;
     double jsq;
-    rc = upload_couplings(b, J, st, &jsq);
+    rc = upload_couplings(b, J, Jz, st, &jsq);
     if (rc) return rc;
     const int64_t D = b->db.dim;
     *n_done = 0;
@@ -1297,7 +1306,7 @@ extern "C" int ed_internal_apply_stats(const ed_basis *b, int64_t *kept, int64_t
     unsigned long long h[2] = {0, 0};
     hipError_t e = hipMemcpyAsync(d, h, 16, hipMemcpyHostToDevice, st);
     int rc = ED_OK;
-    if (e == hipSuccess && b->db.dim > 0) rc = ed::launch_apply(b, nullptr, nullptr, nullptr, stream, 1, d);
+    if (e == hipSuccess && b->db.dim > 0) rc = ed::launch_apply(b, nullptr, nullptr, nullptr, nullptr, stream, 1, d);
     if (e == hipSuccess && rc == ED_OK) e = hipMemcpyAsync(h, d, 16, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && rc == ED_OK) e = hipStreamSynchronize(st);
     (void)hipFree(d);

@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(KB > 16 ? 512 : 1024)
         const int n_terms = row_ok ? __popcll(am.w0) + __popcll(am.w1) + __popcll(am.w2) + __popcll(am.w3) : 0;
         for (int term = 0; term < n_terms; ++term) {
             const BondLds bd = c.bonds[pop_bond(am)];
-            anti_sum += bd.jhalf;
+            anti_sum += bd.jzhalf;
             uint32_t g;
             const uint64_t r = rep_search<AT, NS>(c, s ^ bd.mask, g);
             uint64_t sl = slot_of_state(r, db.slot_log2);
@@ -533,7 +533,7 @@ int multi_apply(const ed_multi *mb, const double *J, const void *x, void *y, voi
     int rc = check_couplings(b, J);
     if (rc) return rc;
     double jsq = 0.0;
-    rc = upload_couplings(b, J, st, &jsq);
+    rc = upload_couplings(b, J, nullptr, st, &jsq);
     if (rc) return rc;
     if (b->db.dim == 0) return ED_OK;
     return multi_launch<0>(mb, x, y, nullptr, nullptr, nullptr, jsq, st);
@@ -617,7 +617,7 @@ int multi_lanczos(ed_multi *mb, const double *J, const void *v0, int n_steps, do
     int rc = check_couplings(b, J);
     if (rc) return rc;
     double jsq = 0.0;
-    rc = upload_couplings(b, J, st, &jsq);
+    rc = upload_couplings(b, J, nullptr, st, &jsq);
     if (rc) return rc;
     if (D == 0 || n_steps <= 0) return ED_OK;
     const int R = kMlzThreads / K;

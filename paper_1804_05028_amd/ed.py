@@ -85,21 +85,29 @@ class Basis:
         if not (v.is_cuda and v.is_contiguous() and v.dtype == self.dtype and v.numel() == self.dim):
             raise ValueError(f"{name} must be a contiguous CUDA {self.dtype} tensor of length {self.dim}")
 
-    def apply(self, J, x, out=None):
-        """y = H(J) x (J on the host, constant on bond orbits)."""
+    def apply(self, J, x, out=None, Jz=None):
+        """y = H(J) x (J on the host, constant on bond orbits); with Jz the
+        XXZ Hamiltonian (exchange J, Ising part Jz)."""
         self._check_vec(x, "x")
         y = self.empty() if out is None else out
         self._check_vec(y, "out")
-        L.ed_apply_H(self.handle, np.asarray(J, np.float64), x, y, _stream())
+        if Jz is None:
+            L.ed_apply_H(self.handle, np.asarray(J, np.float64), x, y, _stream())
+        else:
+            L.ed_apply_H_xxz(self.handle, np.asarray(J, np.float64), np.asarray(Jz, np.float64), x, y, _stream())
         return y
 
     def stats(self):
         return L.ed_apply_H_stats(self.handle, _stream())
 
-    def lanczos(self, J, v0, n_steps, want_psi0=False):
+    def lanczos(self, J, v0, n_steps, want_psi0=False, Jz=None):
         self._check_vec(v0, "v0")
         psi = self.empty() if want_psi0 else None
-        a, b, n = L.ed_lanczos(self.handle, np.asarray(J, np.float64), v0, n_steps, psi, _stream())
+        if Jz is None:
+            a, b, n = L.ed_lanczos(self.handle, np.asarray(J, np.float64), v0, n_steps, psi, _stream())
+        else:
+            a, b, n = L.ed_lanczos_xxz(self.handle, np.asarray(J, np.float64), np.asarray(Jz, np.float64), v0,
+                                       n_steps, psi, _stream())
         ev, _ = L.ed_tridiag_eigh(a, b, want_vec=False) if n else (np.array([]), None)
         return dict(alpha=a, beta=b, n_done=n, eigenvalues=ev, psi0=psi)
 

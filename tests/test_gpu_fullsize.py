@@ -44,6 +44,7 @@ FULL = [
     ("square32_disorder", _disorder, 18_784_998),
     ("triangular36_k1", lambda: wl.triangular_36_momentum(1, n_sub=4), None),
     ("square40_j1j2", lambda: wl.square_40_j1j2(n_sub=4), 430_909_650),
+    ("square40_j1j2j3", lambda: wl.square_40_j1j2j3(n_sub=4), 430_909_650),
 ]
 
 

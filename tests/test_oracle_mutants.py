@@ -25,8 +25,10 @@ MUTANTS = {
     "inverted_norm_ratio": ("sqrt((double)stab[i] / (double)stab[j])",
                             "sqrt((double)stab[j] / (double)stab[i])"),
     "lsb_site_order": ("return (int)((s >> (n - 1 - site)) & 1ull);", "return (int)((s >> site) & 1ull);"),
-    "diagonal_sign": ("d += same ? 0.25 * J[b] : -0.25 * J[b];\n        }\n        yt",
-                      "d += same ? -0.25 * J[b] : 0.25 * J[b];\n        }\n        yt"),
+    "diagonal_sign": ("d += same ? 0.25 * Jz[b] : -0.25 * Jz[b];\n        }\n        yt",
+                      "d += same ? -0.25 * Jz[b] : 0.25 * Jz[b];\n        }\n        yt"),
+    "ising_uses_exchange": ("d += same ? 0.25 * Jz[b] : -0.25 * Jz[b];\n        }\n        yt",
+                            "d += same ? 0.25 * J[b] : -0.25 * J[b];\n        }\n        yt"),
     "ignore_compatibility": ("                if (comp) {\n                    if (want)",
                              "                if (1) {\n                    if (want)"),
     "action_inverse": ("if (get_bit(s, n, i)) r |= 1ull << (n - 1 - perm[i]);",
@@ -50,6 +52,14 @@ def _build_mutant(tmp_path, name):
     return path
 
 
+def xx_ring_ground_energy(n, n_up, jxy=1.0):
+    """XX ring by the Jordan-Wigner map: free fermions with hopping jxy/2,
+    periodic for an odd particle number and antiperiodic for an even one."""
+    shift = 0.0 if n_up % 2 == 1 else 0.5
+    eps = sorted(jxy * math.cos(2 * math.pi * (m + shift) / n) for m in range(n))
+    return sum(eps[:n_up])
+
+
 def _pins_pass():
     """The oracle pins in compact form; True if all of them hold."""
     ok = True
@@ -68,6 +78,16 @@ def _pins_pass():
             H = np.stack([bf.apply(m, st, stab, e.astype(complex))[0] for e in np.eye(len(st))], 1)
             best = min(best, np.linalg.eigvalsh((H + H.conj().T) / 2)[0])
     ok &= abs(best - (-1 - math.sqrt(13) / 2)) < 1e-10
+    # XX ring (Jz = 0): free-fermion ground energy over all momenta
+    c = lat.chain(8)
+    best = 1e9
+    for k in range(8):
+        m = bf.Model(8, c.perm, c.flip, lat.characters(c, k), c.bonds, np.ones(8), np.zeros(8))
+        st, stab = bf.basis(m, 4)
+        if len(st):
+            H = np.stack([bf.apply(m, st, stab, e.astype(complex))[0] for e in np.eye(len(st))], 1)
+            best = min(best, np.linalg.eigvalsh((H + H.conj().T) / 2)[0])
+    ok &= abs(best - xx_ring_ground_energy(8, 4)) < 1e-10
     # definition-level matrices: complex momentum on the 8-ring, full group on 12-site triangular
     cases = []
     c8 = lat.chain(8)
