@@ -80,14 +80,17 @@ def _workload(name, n_sub):
     raise SystemExit(f"unknown workload {name}")
 
 
-def _allk_workloads(n_sub):
-    """The 20 inequivalent momentum sectors of the 36-site triangular cluster
-    with translations only: Gamma, the three M points and one momentum of every
-    +-k pair (for real H the sector -k is the complex conjugate of sector k)."""
+def _allk_workloads(n_sub, which="all"):
+    """Momentum sectors of the 36-site triangular cluster with translations
+    only: all 36, or the 20 inequivalent ones (Gamma, the three M points and
+    one momentum of every +-k pair; for real H the sector -k is the complex
+    conjugate of sector k)."""
     from ed_inputs import lattice as lat
     from ed_inputs import workloads as wl
     w0 = wl.triangular_36_momentum(0, n_sub=n_sub or 4)
-    ks = [k for k in range(w0.cluster.n_elems) if k <= lat.conjugate_momentum_index(w0.cluster, k)]
+    ks = range(w0.cluster.n_elems)
+    if which == "inequivalent":
+        ks = [k for k in ks if k <= lat.conjugate_momentum_index(w0.cluster, k)]
     return [wl.triangular_36_momentum(k, n_sub=n_sub or 4) for k in ks]
 
 
@@ -95,7 +98,7 @@ def bench_allk(args):
     """Batched all-sector H.v and Lanczos against one launch per sector."""
     import torch
     from paper_1804_05028_amd import ed
-    ws = _allk_workloads(args.n_sub)
+    ws = _allk_workloads(args.n_sub, args.sectors)
     J = ws[0].J
     reps = max(args.hv_reps, 1)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -176,7 +179,8 @@ def bench_allk(args):
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": "triangular36_allk", "n_sectors": len(ws), "batch": args.batch,
-                   "description": "Heisenberg triangular 36 (6,0)x(0,6), 36 T, 20 inequivalent momenta, Sz=0",
+                   "description": f"Heisenberg triangular 36 (6,0)x(0,6), 36 T, {len(ws)} momentum sectors "
+                                  f"({args.sectors}), Sz=0",
                    "shared_rows": info["dim"] if info else 0, "n_sublat": info["n_sublat"] if info else 0,
                    "parallelism": "1 GPU"},
         "batched_hv_ms": hv_ms,
@@ -226,7 +230,9 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="build, then run --hv-reps H.v launches only")
-    ap.add_argument("--batch", type=int, default=10, help="sectors per batched launch (triangular36_allk)")
+    ap.add_argument("--batch", type=int, default=18, help="sectors per batched launch (triangular36_allk)")
+    ap.add_argument("--sectors", default="all", choices=["all", "inequivalent"],
+                    help="triangular36_allk: all 36 momenta, or the 20 inequivalent ones")
     ap.add_argument("--autotune", action="store_true",
                     help="search sublattice decompositions and launch tunings first, then bench the fastest")
     args = ap.parse_args()

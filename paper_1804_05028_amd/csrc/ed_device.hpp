@@ -178,12 +178,17 @@ __device__ __forceinline__ uint64_t find_rep(const Ctx<AT> &c, uint64_t s, uint3
     return best;
 }
 
-// The same search with the number of sublattices fixed at compile time: the
-// substate blocks stay in registers and the block loops unroll.
-template <typename AT, int NS>
+// The same search with the number of sublattices (and, if NC > 0, the number
+// of action-table chunks) fixed at compile time: the substate blocks stay in
+// registers and the block and chunk loops unroll.  Every block of a candidate
+// is assembled, the one landing on top included, so that the table reads of
+// a candidate are independent and issue together; the top block is then
+// replaced by MinRep, and the flip applied to the rest.
+template <typename AT, int NS, int NC>
 __device__ __forceinline__ uint64_t find_rep_ns(const Ctx<AT> &c, uint64_t s, uint32_t &g_best)
 {
-    const int N = c.N, m = c.m;
+    const int N = c.N, m = c.m, cb = c.cb;
+    const int nc = NC > 0 ? NC : c.nc;
     const uint32_t P = c.mmask + 1;
     uint32_t sx[NS];
     uint32_t minr = 0xFFFFFFFFu;
@@ -207,18 +212,22 @@ __device__ __forceinline__ uint64_t find_rep_ns(const Ctx<AT> &c, uint64_t s, ui
         for (uint32_t k = 1; k <= cnt; ++k) {
             const uint32_t ent = c.sym[off + k];
             const uint32_t u = (ent >> 16) & 0x7FFFu;
-            const AT *tu = c.act + ((size_t)u * NS * c.nc << c.cb);
+            const AT *tu = c.act + ((size_t)u * NS * nc << cb);
             uint64_t v = 0;
 #pragma unroll
             for (int X = 0; X < NS; ++X) {
-                if (X == Y) continue;
-                const AT *t = tu + ((X * c.nc) << c.cb);
+                const AT *t = tu + ((X * nc) << cb);
                 uint32_t blk = 0;
-                for (int k2 = 0; k2 < c.nc; ++k2) blk |= t[(k2 << c.cb) | ((sx[X] >> (k2 * c.cb)) & c.cmask)];
+                if (NC > 0) {
+#pragma unroll
+                    for (int k2 = 0; k2 < (NC > 0 ? NC : 1); ++k2)
+                        blk |= t[(k2 << cb) | ((sx[X] >> (k2 * cb)) & c.cmask)];
+                } else {
+                    for (int k2 = 0; k2 < nc; ++k2) blk |= t[(k2 << cb) | ((sx[X] >> (k2 * cb)) & c.cmask)];
+                }
                 v |= place_block(c, u, NS, X, blk);
             }
-            if (ent >> 31) v ^= c.low_mask;
-            v |= top;
+            v = ((v ^ ((ent >> 31) ? ~0ull : 0ull)) & c.low_mask) | top;
             if (v < best) {
                 best = v;
                 bg = ent & 0xFFFFu;
@@ -229,10 +238,13 @@ __device__ __forceinline__ uint64_t find_rep_ns(const Ctx<AT> &c, uint64_t s, ui
     return best;
 }
 
-template <typename AT, int NS>
+// NSC = NS * 8 + NC: sublattices and chunks fixed at compile time (0 = read
+// them at run time; NC = 0 with NS > 0 fixes only the sublattice count)
+template <typename AT, int NSC>
 __device__ __forceinline__ uint64_t rep_search(const Ctx<AT> &c, uint64_t s, uint32_t &g)
 {
-    if (NS > 0) return find_rep_ns<AT, (NS > 0 ? NS : 1)>(c, s, g);
+    constexpr int NS = NSC / 8, NC = NSC % 8;
+    if (NS > 0) return find_rep_ns<AT, (NS > 0 ? NS : 1), NC>(c, s, g);
     uint32_t mv;
     return find_rep(c, s, g, mv);
 }
@@ -240,14 +252,13 @@ __device__ __forceinline__ uint64_t rep_search(const Ctx<AT> &c, uint64_t s, uin
 // ---------------------------------------------------------------------------
 // index lookups
 // ---------------------------------------------------------------------------
-// home slot of a state: MurmurHash3's 64-bit finaliser (Appleby), top bits
+// home slot of a state: multiplicative (Fibonacci) hashing, the top log2n
+// bits of s * floor(2^64 / golden ratio) (Knuth, TAOCP vol. 3, sec. 6.4).
+// One 64-bit multiply; a bit of s changes the product at its position and
+// above, so the top bits depend on every state bit.
 __device__ __forceinline__ uint64_t slot_of_state(uint64_t s, int log2n)
 {
-    s ^= s >> 33;
-    s *= 0xff51afd7ed558ccdull;
-    s ^= s >> 33;
-    s *= 0xc4ceb9fe1a85ec53ull;
-    s ^= s >> 33;
+    s *= 0x9e3779b97f4a7c15ull;
     return log2n ? (s >> (64 - log2n)) : 0ull;
 }
 

@@ -21,8 +21,8 @@ namespace ed {
 // ---------------------------------------------------------------------------
 // H.v, gather form of the parallel matrix-vector multiply:
 //   y_i = d_i x_i + sum_{b antiparallel} (J_b/2) chi(g) sqrt(n_j/n_i) x_j
-// One thread per row, persistent blocks, every y_i written once.  NS > 0
-// fixes the number of sublattices at compile time (0: read it at run time).
+// One thread per row, persistent blocks, every y_i written once.  NS encodes
+// sublattices * 8 + chunks fixed at compile time (0: read at run time).
 // MODE 0: y = H x.  MODE 1: count kept/dropped terms.  MODE 2: Lanczos
 // w = H v - beta_prev v_prev with per-block <v, w> partial sums.
 // ---------------------------------------------------------------------------
@@ -58,26 +58,61 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
         am.w2 = nb > 128 ? bond_word(c, s, 2, nb) : 0ull;
         am.w3 = nb > 192 ? bond_word(c, s, 3, nb) : 0ull;
         const int n_terms = row_ok ? __popcll(am.w0) + __popcll(am.w1) + __popcll(am.w2) + __popcll(am.w3) : 0;
-        if (INDEX == IDX_HASH) {
-            for (int term = 0; term < n_terms; ++term) {
+        if (INDEX == IDX_HASH && MODE != 1) {
+            // software pipeline: the slot of the next term is requested before
+            // the current term is resolved, so the random read overlaps the
+            // next representative search
+            uint64_t r_nx = 0, sl_nx = 0;
+            uint32_t g_nx = 0;
+            double jh_nx = 0.0;
+            ulonglong2 q_nx = make_ulonglong2(0ull, 0ull);
+            if (n_terms > 0) {
                 const BondLds bd = c.bonds[pop_bond(am)];
                 anti_sum += bd.jzhalf;
+                jh_nx = bd.jhalf;
+                r_nx = rep_search<AT, NS>(c, s ^ bd.mask, g_nx);
+                sl_nx = slot_of_state(r_nx, db.slot_log2);
+                q_nx = load_slot<CPLX>(db.slots, sl_nx);
+            }
+            for (int term = 0; term < n_terms; ++term) {
+                const uint64_t r = r_nx, sl = sl_nx;
+                const uint32_t g = g_nx;
+                const double jh = jh_nx;
+                const ulonglong2 q = q_nx;
+                if (term + 1 < n_terms) {
+                    const BondLds bd = c.bonds[pop_bond(am)];
+                    anti_sum += bd.jzhalf;
+                    jh_nx = bd.jhalf;
+                    r_nx = rep_search<AT, NS>(c, s ^ bd.mask, g_nx);
+                    sl_nx = slot_of_state(r_nx, db.slot_log2);
+                    q_nx = load_slot<CPLX>(db.slots, sl_nx);
+                }
+                uint64_t key;
+                double vr, vi;
+                if (!resolve_slot<CPLX>(db, q, sl, r, key, vr, vi)) {
+                    ++dropped;
+                    continue;
+                }
+                ++kept;
+                double cr, ci;
+                chi_of<CPLX>(c, g, cr, ci);
+                const double amp = jh * rs_i * c.div_sqrt[key >> kNormShift];
+                ar += amp * (cr * vr - ci * vi);
+                if (CPLX) ai += amp * (cr * vi + ci * vr);
+            }
+        } else if (INDEX == IDX_HASH) {
+            // term counting
+            for (int term = 0; term < n_terms; ++term) {
+                const BondLds bd = c.bonds[pop_bond(am)];
                 uint32_t g;
                 const uint64_t r = rep_search<AT, NS>(c, s ^ bd.mask, g);
                 const uint64_t sl = slot_of_state(r, db.slot_log2);
                 uint64_t key;
                 double vr, vi;
-                if (!resolve_slot<CPLX>(db, load_slot<CPLX>(db.slots, sl), sl, r, key, vr, vi)) {
+                if (resolve_slot<CPLX>(db, load_slot<CPLX>(db.slots, sl), sl, r, key, vr, vi))
+                    ++kept;
+                else
                     ++dropped;
-                    continue;
-                }
-                ++kept;
-                if (MODE == 1) continue;
-                double cr, ci;
-                chi_of<CPLX>(c, g, cr, ci);
-                const double amp = bd.jhalf * rs_i * c.div_sqrt[key >> kNormShift];
-                ar += amp * (cr * vr - ci * vi);
-                if (CPLX) ai += amp * (cr * vi + ci * vr);
             }
         } else {
             for (int term = 0; term < n_terms; ++term) {
@@ -1040,8 +1075,15 @@ static int apply_ns(const ed_basis *b, const void *x, void *y, const void *vprev
                     unsigned long long *stats, const LzState *lz, double jsq, hipStream_t st)
 {
 #define ED_NS(K) \
-    case K: return apply_impl<CPLX, AT, IDX_HASH, MODE, K>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    case K: return apply_impl<CPLX, AT, IDX_HASH, MODE, K * 8>(b, x, y, vprev, partials, stats, lz, jsq, st);
     if (MODE != 1) {
+        // four sublattices with one to three chunks: chunk count fixed too
+        if (b->dm.ns == 4 && b->dm.n_chunks == 1)
+            return apply_impl<CPLX, AT, IDX_HASH, MODE, 33>(b, x, y, vprev, partials, stats, lz, jsq, st);
+        if (b->dm.ns == 4 && b->dm.n_chunks == 2)
+            return apply_impl<CPLX, AT, IDX_HASH, MODE, 34>(b, x, y, vprev, partials, stats, lz, jsq, st);
+        if (b->dm.ns == 4 && b->dm.n_chunks == 3)
+            return apply_impl<CPLX, AT, IDX_HASH, MODE, 35>(b, x, y, vprev, partials, stats, lz, jsq, st);
         switch (b->dm.ns) {
             ED_NS(2) ED_NS(3) ED_NS(4) ED_NS(5) ED_NS(6) ED_NS(8) ED_NS(9) ED_NS(10)
         default: break;

@@ -108,7 +108,7 @@ __global__ void k_multi_pack_index(const uint32_t *slot_of, const uint64_t *mask
 // shared kept terms in stats[K], dropped lookups in stats[K+1].
 // ---------------------------------------------------------------------------
 template <typename AT, int NS, int KB, int MODE>
-__global__ void __launch_bounds__(KB > 16 ? 512 : 1024)
+__global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
     k_apply_multi(DevModel dm, DevBasis db, MultiDev md, const double2 *__restrict__ x, double2 *y,
                   const double2 *vprev, const MlzSector *__restrict__ sec, double *stats, double jsq)
 {
@@ -153,13 +153,34 @@ __global__ void __launch_bounds__(KB > 16 ? 512 : 1024)
         am.w2 = nb > 128 ? bond_word(c, s, 2, nb) : 0ull;
         am.w3 = nb > 192 ? bond_word(c, s, 3, nb) : 0ull;
         const int n_terms = row_ok ? __popcll(am.w0) + __popcll(am.w1) + __popcll(am.w2) + __popcll(am.w3) : 0;
-        for (int term = 0; term < n_terms; ++term) {
+        // software pipeline: the slot of the next term is requested before
+        // the current term is resolved
+        uint64_t r_nx = 0, sl_nx = 0;
+        uint32_t g_nx = 0;
+        double jh_nx = 0.0;
+        ulonglong2 q_nx = make_ulonglong2(0ull, 0ull);
+        if (n_terms > 0) {
             const BondLds bd = c.bonds[pop_bond(am)];
             anti_sum += bd.jzhalf;
-            uint32_t g;
-            const uint64_t r = rep_search<AT, NS>(c, s ^ bd.mask, g);
-            uint64_t sl = slot_of_state(r, db.slot_log2);
-            ulonglong2 q = load_slot<false>(db.slots, sl);
+            jh_nx = bd.jhalf;
+            r_nx = rep_search<AT, NS>(c, s ^ bd.mask, g_nx);
+            sl_nx = slot_of_state(r_nx, db.slot_log2);
+            q_nx = load_slot<false>(db.slots, sl_nx);
+        }
+        for (int term = 0; term < n_terms; ++term) {
+            const uint64_t r = r_nx;
+            uint64_t sl = sl_nx;
+            const uint32_t g = g_nx;
+            const double jh = jh_nx;
+            ulonglong2 q = q_nx;
+            if (term + 1 < n_terms) {
+                const BondLds bd = c.bonds[pop_bond(am)];
+                anti_sum += bd.jzhalf;
+                jh_nx = bd.jhalf;
+                r_nx = rep_search<AT, NS>(c, s ^ bd.mask, g_nx);
+                sl_nx = slot_of_state(r_nx, db.slot_log2);
+                q_nx = load_slot<false>(db.slots, sl_nx);
+            }
             while (q.x != kEmpty && (q.x & kStateMask) != r) {
                 sl = (sl + 1) & smask;
                 q = load_slot<false>(db.slots, sl);
@@ -175,7 +196,7 @@ __global__ void __launch_bounds__(KB > 16 ? 512 : 1024)
                 for (int k = 0; k < KB; ++k) ar[k] += (double)((mij >> k) & 1ull);
                 continue;
             }
-            const double amp = bd.jhalf * rs_i * c.div_sqrt[q.x >> kNormShift];
+            const double amp = jh * rs_i * c.div_sqrt[q.x >> kNormShift];
             const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K;
             const double2 *ch = chik + (size_t)g * K;
 #pragma unroll
@@ -409,7 +430,7 @@ static int multi_launch_impl(const ed_multi *mb, const void *x, void *y, const v
 {
     const ed_basis *b = mb->base;
     auto kern = k_apply_multi<AT, NS, KB, MODE>;
-    const int bound = KB > 16 ? 512 : 1024;
+    const int bound = KB > 8 ? 512 : 1024;
     int threads = b->tuning.block_threads > 0 ? std::min(b->tuning.block_threads, bound) : bound;
     MultiDev md;
     md.K = mb->K;
@@ -447,13 +468,16 @@ static int multi_launch(const ed_multi *mb, const void *x, void *y, const void *
                         double jsq, hipStream_t st)
 {
     const ed_basis *b = mb->base;
-    const bool ns4 = MODE == 0 && b->dm.ns == 4;
+    // four sublattices with one or two chunks: search loops fixed at compile time
+    const int nsc = (MODE == 0 && b->dm.ns == 4 && b->dm.n_chunks <= 2) ? 32 + b->dm.n_chunks : 0;
     if (table_width(b) == 2) {
-        if (ns4) return multi_launch_kb<MODE, uint16_t, 4>(mb, x, y, vprev, sec, stats, jsq, st);
+        if (nsc == 33) return multi_launch_kb<MODE, uint16_t, 33>(mb, x, y, vprev, sec, stats, jsq, st);
+        if (nsc == 34) return multi_launch_kb<MODE, uint16_t, 34>(mb, x, y, vprev, sec, stats, jsq, st);
         return multi_launch_kb<MODE, uint16_t, 0>(mb, x, y, vprev, sec, stats, jsq, st);
     }
     if (table_width(b) == 4) {
-        if (ns4) return multi_launch_kb<MODE, uint32_t, 4>(mb, x, y, vprev, sec, stats, jsq, st);
+        if (nsc == 33) return multi_launch_kb<MODE, uint32_t, 33>(mb, x, y, vprev, sec, stats, jsq, st);
+        if (nsc == 34) return multi_launch_kb<MODE, uint32_t, 34>(mb, x, y, vprev, sec, stats, jsq, st);
         return multi_launch_kb<MODE, uint32_t, 0>(mb, x, y, vprev, sec, stats, jsq, st);
     }
     return set_error(ED_ERR_UNSUPPORTED, "batched sectors need 2- or 4-byte action-table entries");
