@@ -40,44 +40,33 @@ BYTES_ROW_CPLX, BYTES_TERM_CPLX = 41.0, 25.0
 
 # Measured HBM bytes per H.v launch: FETCH_SIZE and WRITE_SIZE runs of
 # rocprofv3, scaled by what the same counters read for a plain device copy of
-# known size (x2.0 and x1.0).  A figure is valid only for the kernel source it
-# was taken on (sha256 of csrc/ed_kernels.hip) and the same configuration;
-# otherwise the roofline reports traffic as null.
-KERNEL_SRC = os.path.join(ROOT, "paper_1804_05028_amd", "csrc", "ed_kernels.hip")
+# known size (x2.0 and x1.0).  A figure is valid only for the kernel sources it
+# was taken on (sha256 of ed_kernels.hip + ed_device.hpp + ed_internal.hpp,
+# concatenated) and the same configuration; otherwise traffic is reported as
+# null.
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_05028_amd", "csrc", f)
+               for f in ("ed_kernels.hip", "ed_device.hpp", "ed_internal.hpp")]
 MEASURED_TRAFFIC = {
     # (workload, n_sublat, index, chunk_bits): (kernel sha256, fetch bytes, write bytes)
     ("square40_j1j2", 4, "hash-slot", 5): (
-        "fb3db0fc9adac8c44f56739139a84db89f6f9b8c4e6e6594ac0cc8b55e164095", 5.197e12, 3.447e9),
+        "c1f5ce1b9104ef568e542dedc8afb6dfb7bb3c1a36757da061ea482657a6203b", 4.93050e12, 3.4473e9),
 }
 
 
-def measured_traffic(key):
+def kernel_digest():
     import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key):
     rec = MEASURED_TRAFFIC.get(key)
     if rec is None:
         return None
-    with open(KERNEL_SRC, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
-    return rec[1] + rec[2] if digest == rec[0] else None
-
-
-AUTOTUNE_NSUB = {"square40_j1j2": [4, 5], "square40_j1j2j3": [4, 5], "triangular36": [3, 4], "square32_disorder": [4, 8], "square16": [2, 4]}
-
-
-def _workload(name, n_sub):
-    from ed_inputs import workloads as wl
-    if name == "square40_j1j2":
-        return wl.square_40_j1j2(n_sub=n_sub or 4), "J1-J2 square 40 (6,2)x(-2,6), 40T x C4 x flip, Gamma.A.even, Sz=0"
-    if name == "square40_j1j2j3":
-        return (wl.square_40_j1j2j3(n_sub=n_sub or 4),
-                "J1-J2-J3 square 40 (6,2)x(-2,6), J2=0.5 J3=0.25, 40T x C4 x flip, Gamma.A.even, Sz=0")
-    if name == "triangular36":
-        return wl.triangular_36(n_sub=n_sub or 4), "Heisenberg triangular 36 (6,0)x(0,6), 36T x C6v x flip, Gamma.A1.even, Sz=0"
-    if name == "square32_disorder":
-        return wl.square_32_disorder(n_sub=n_sub or 4), "Heisenberg square 32 (4,4)x(-4,4), 32T, k=0, orbit-averaged J_b"
-    if name == "square16":
-        return wl.square_4x4(n_sub=n_sub or 4), "Heisenberg square 16 (4x4), 16T, k=0, Sz=0"
-    raise SystemExit(f"unknown workload {name}")
+    return rec[1] + rec[2] if kernel_digest() == rec[0] else None
 
 
 def _allk_workloads(n_sub, which="all"):
