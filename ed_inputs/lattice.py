@@ -227,6 +227,79 @@ def build_cluster(name, L1, L2, bond_vectors, point_group_gens=(), spin_flip=Fal
 
 
 # --------------------------------------------------------------------------
+# sublattice decompositions
+# --------------------------------------------------------------------------
+
+
+def _hnf(M1, M2):
+    """Hermite normal form ((a, 0), (b, d)), a, d > 0, 0 <= b < a, of the
+    lattice spanned by M1, M2 (the unique basis of that shape)."""
+    import math
+    # column operations on [M1 M2] (2x2 integer) to lower-triangular form
+    (x1, y1), (x2, y2) = M1, M2
+    # make the second coordinate of the first vector 0 by the Euclidean algorithm on y
+    while y1 != 0:
+        q = y2 // y1
+        x2, y2 = x2 - q * x1, y2 - q * y1
+        x1, y1, x2, y2 = x2, y2, x1, y1
+    a, b, d = x1, x2, y2
+    if a < 0:
+        a = -a
+    if d < 0:
+        b, d = -b, -d
+    b %= a
+    _ = math
+    return ((a, 0), (b, d))
+
+
+def _in_lattice(p, a, b, d):
+    if p[1] % d:
+        return False
+    v = p[1] // d
+    return (p[0] - v * b) % a == 0
+
+
+def stable_superlattices(L1, L2, point_group, n_sub):
+    """Every superlattice M of index n_sub in Z^2 that contains the cluster's
+    period lattice and is mapped onto itself by every point-group matrix.
+
+    Its cosets are sublattices that every group element maps onto
+    sublattices: a translation permutes the cosets, and R (p + M) = Rp + M
+    when RM = M, which is the sublattice stability of sec. "Generic
+    sublattice coding algorithm".  Returned as Hermite-normal-form bases
+    ((a, 0), (b, d)) with a * d = n_sub, 0 <= b < a, in a fixed order.
+    """
+    out = []
+    for a in range(1, n_sub + 1):
+        if n_sub % a:
+            continue
+        d = n_sub // a
+        for b in range(a):
+            if not (_in_lattice(L1, a, b, d) and _in_lattice(L2, a, b, d)):
+                continue
+            ok = True
+            for R in point_group:
+                for v in ((a, 0), (b, d)):
+                    if not _in_lattice(_mat_apply(R, v), a, b, d):
+                        ok = False
+            if ok:
+                out.append(((a, 0), (b, d)))
+    return out
+
+
+def sublattice_decompositions(L1, L2, point_group, n_sites, max_sub_sites=16):
+    """(n_sub, superlattice) for every sublattice-stable superlattice with at
+    most max_sub_sites sites per sublattice, fewest sublattices first."""
+    out = []
+    for n_sub in range(1, n_sites + 1):
+        if n_sites % n_sub or n_sites // n_sub > max_sub_sites:
+            continue
+        for M in stable_superlattices(L1, L2, point_group, n_sub):
+            out.append((n_sub, M))
+    return out
+
+
+# --------------------------------------------------------------------------
 # named lattice families
 # --------------------------------------------------------------------------
 

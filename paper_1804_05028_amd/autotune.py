@@ -50,7 +50,8 @@ def _time_apply(basis, J, reps):
 def autotune(make_workload, n_subs, candidates=None, reps=2, time_limit_s=None, log=None):
     """Return (best, results).
 
-    make_workload(n_sub) -> workload for one sublattice decomposition;
+    make_workload(key) -> workload for one sublattice decomposition (key is
+    n_sub, or any label such as an (n_sub, superlattice) pair);
     candidates(sub_bits) -> list of tuning dicts (default_candidates if None).
     best = {"n_sub", "tuning", "hv_ms", "info"}; results lists every trial.
     """
@@ -59,7 +60,7 @@ def autotune(make_workload, n_subs, candidates=None, reps=2, time_limit_s=None, 
     t_start = time.perf_counter()
     for ns in n_subs:
         w = make_workload(ns)
-        sub_bits = w.cluster.n_sites // ns
+        sub_bits = w.cluster.n_sites // w.cluster.n_sublat
         for tn in candidates(sub_bits):
             if time_limit_s is not None and time.perf_counter() - t_start > time_limit_s:
                 break
@@ -86,6 +87,22 @@ def autotune(make_workload, n_subs, candidates=None, reps=2, time_limit_s=None, 
         raise RuntimeError("no candidate configuration could be built")
     best = min(timed, key=lambda r: r["hv_ms"])
     return best, results
+
+
+def autotune_decompositions(make_workload_for, decompositions, n_up, top=3, **kw):
+    """Rank sublattice decompositions on the host (decompose.rank_decompositions),
+    then time the best `top` of them with every candidate tuning.
+
+    make_workload_for(superlattice) -> workload whose cluster uses that
+    superlattice; decompositions: (n_sub, superlattice) pairs, e.g. from
+    ed_inputs.lattice.sublattice_decompositions.  Returns (best, results,
+    ranking); best["n_sub"] is the (n_sub, superlattice) pair.
+    """
+    from . import decompose
+    ranked = decompose.rank_decompositions(lambda M: make_workload_for(M).cluster, decompositions, n_up)
+    keys = [(r["n_sub"], r["superlattice"]) for r in ranked if r["fits"]][:top]
+    best, results = autotune(lambda key: make_workload_for(key[1]), keys, **kw)
+    return best, results, ranked
 
 
 def speedup_table(results):

@@ -31,3 +31,31 @@ def test_autotune_picks_a_valid_configuration():
         assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
     finally:
         b.close()
+
+
+def test_autotune_over_enumerated_decompositions():
+    """Host ranking of the stable decompositions, then GPU timing of the best two."""
+    from paper_1804_05028_amd import autotune as at
+    from paper_1804_05028_amd import ed
+    from ed_inputs import lattice as lat
+
+    def make(M):
+        c = lat.square((4, 2), (-2, 4), j2=True, spin_flip=True, superlattice=M, name="square20")
+        J = np.array([1.0, 0.5])[c.bond_kind]
+        return wl.Workload("square20_j1j2", c, lat.characters(c, 0), 10, J)
+
+    base = lat.square((4, 2), (-2, 4), j2=True, spin_flip=True, name="square20")
+    decs = lat.sublattice_decompositions((4, 2), (-2, 4), base.point_group, 20, 12)
+    best, results, ranking = at.autotune_decompositions(make, decs, 10, top=2, reps=2)
+    assert len({r["n_sub"] for r in results}) <= 2
+    w = make(best["n_sub"][1])
+    b = ed.Basis.from_workload(w, best["tuning"])
+    try:
+        m = bf.Model.from_workload(w)
+        st, stab = bf.basis(m, w.n_up)
+        x = vec.normal_vector(len(st), seed=12)
+        y = b.apply(w.J, torch.as_tensor(x).cuda()).cpu().numpy()
+        ref, _, _ = bf.apply(m, st, stab, x)
+        assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
+    finally:
+        b.close()

@@ -220,3 +220,44 @@ def test_tridiag_eigh_matches_numpy():
         w, V = np.linalg.eigh(T)
         assert np.abs(ev - w).max() < 1e-12 * max(1, np.abs(w).max())
         assert abs(abs(vec @ V[:, 0]) - 1) < 1e-10
+
+
+def test_validate_limits_and_malformed_input():
+    c = lat.chain(40, superlattice_period=2)
+    _expect("ED_ERR_UNSUPPORTED", lambda: L.ed_tables_create(L.ModelArrays(40, c.bonds, 2, c.perm, c.flip)))
+    c = lat.chain(20)
+    many = np.concatenate([c.bonds] * 13)          # 260 bonds
+    _expect("ED_ERR_UNSUPPORTED",
+            lambda: L.ed_validate(L.ModelArrays(20, many, 1, c.perm, c.flip, lat.characters(c, 0)), 10))
+    c = lat.chain(57, superlattice_period=3)
+    _expect("ED_ERR_UNSUPPORTED",
+            lambda: L.ed_validate(L.ModelArrays(57, c.bonds, c.n_sublat, c.perm, c.flip, lat.characters(c, 0)), 28))
+    c = lat.chain(8)
+    chi = lat.characters(c, 0)
+    for bad in ([3, 3], [3, 9]):
+        bb = c.bonds.copy()
+        bb[0] = bad
+        _expect("ED_ERR_ARG", lambda: L.ed_validate(L.ModelArrays(8, bb, 1, c.perm, c.flip, chi), 4))
+    _expect("ED_ERR_ARG", lambda: L.ed_validate(L.ModelArrays(8, c.bonds, 1, c.perm, c.flip, chi), 9))
+    pp = c.perm.copy()
+    pp[1, 0] = pp[1, 1]
+    _expect("ED_ERR_NOT_GROUP", lambda: L.ed_validate(L.ModelArrays(8, c.bonds, 1, pp, c.flip, chi), 4))
+
+
+def test_host_find_rep_at_the_56_site_limit():
+    """The largest supported N: 56-site ring, 8 sublattices of 7 sites."""
+    c = lat.chain(56, superlattice_period=8)
+    L.ed_validate(L.ModelArrays(56, c.bonds, c.n_sublat, c.perm, c.flip, lat.characters(c, 0)), 28)
+    h = L.ed_tables_create(L.ModelArrays(56, c.bonds, c.n_sublat, c.perm, c.flip))
+    try:
+        rng = np.random.default_rng(11)
+        keys = rng.random((400, 56)).argsort(axis=1)[:, :28]
+        s = np.zeros(400, np.uint64)
+        for k in range(28):
+            s |= np.left_shift(np.uint64(1), (55 - keys[:, k]).astype(np.uint64))
+        r, _, _ = L.ed_tables_find_rep(h, s)
+        m = bf.Model(56, c.perm, c.flip, np.ones(c.n_elems))
+        ref, _, _, _ = bf.rep_many(m, s)
+        assert np.array_equal(r, ref)
+    finally:
+        L.ed_tables_free(h)
