@@ -274,19 +274,31 @@ __device__ __forceinline__ ulonglong2 load_slot(const char *slots, uint64_t sl)
     return make_ulonglong2(v.x, v.y);
 }
 
+// second 16 bytes of a complex slot: the amplitude (re, im)
+__device__ __forceinline__ double2 load_slot_value(const char *slots, uint64_t sl)
+{
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    const f64x2 v = __builtin_nontemporal_load((const f64x2 *)(slots + (sl << 5) + 16));
+    return make_double2(v.x, v.y);
+}
+
 // Probe from the home slot (whose first 16 bytes are q) until the target or
-// an empty slot; returns 1 and the packed key and amplitude if found.
-template <bool CPLX>
+// an empty slot; returns 1 and the packed key and amplitude if found.  For
+// complex slots v_home is the home slot's amplitude, read together with q
+// (HAVE_V) so that a hit on the home slot needs no second, dependent read.
+template <bool CPLX, bool HAVE_V = false>
 __device__ __forceinline__ int resolve_slot(const DevBasis &db, ulonglong2 q, uint64_t sl, uint64_t target,
-                                            uint64_t &key, double &vr, double &vi)
+                                            uint64_t &key, double &vr, double &vi,
+                                            double2 v_home = make_double2(0.0, 0.0))
 {
     const uint64_t smask = (1ull << db.slot_log2) - 1ull;
+    bool home = true;
     while (true) {
         if (q.x == kEmpty) return 0;
         if ((q.x & kStateMask) == target) {
             key = q.x;
             if (CPLX) {
-                const double2 v = *(const double2 *)(db.slots + (sl << 5) + 16);
+                const double2 v = (HAVE_V && home) ? v_home : load_slot_value(db.slots, sl);
                 vr = v.x;
                 vi = v.y;
             } else {
@@ -295,6 +307,7 @@ __device__ __forceinline__ int resolve_slot(const DevBasis &db, ulonglong2 q, ui
             }
             return 1;
         }
+        home = false;
         sl = (sl + 1) & smask;
         q = load_slot<CPLX>(db.slots, sl);
     }

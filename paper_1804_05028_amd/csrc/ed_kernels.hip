@@ -66,6 +66,7 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
             uint32_t g_nx = 0;
             double jh_nx = 0.0;
             ulonglong2 q_nx = make_ulonglong2(0ull, 0ull);
+            double2 v_nx = make_double2(0.0, 0.0);   // complex: home slot's amplitude
             if (n_terms > 0) {
                 const BondLds bd = c.bonds[pop_bond(am)];
                 anti_sum += bd.jzhalf;
@@ -73,12 +74,14 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
                 r_nx = rep_search<AT, NS>(c, s ^ bd.mask, g_nx);
                 sl_nx = slot_of_state(r_nx, db.slot_log2);
                 q_nx = load_slot<CPLX>(db.slots, sl_nx);
+                if (CPLX) v_nx = load_slot_value(db.slots, sl_nx);
             }
             for (int term = 0; term < n_terms; ++term) {
                 const uint64_t r = r_nx, sl = sl_nx;
                 const uint32_t g = g_nx;
                 const double jh = jh_nx;
                 const ulonglong2 q = q_nx;
+                const double2 v = v_nx;
                 if (term + 1 < n_terms) {
                     const BondLds bd = c.bonds[pop_bond(am)];
                     anti_sum += bd.jzhalf;
@@ -86,10 +89,11 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
                     r_nx = rep_search<AT, NS>(c, s ^ bd.mask, g_nx);
                     sl_nx = slot_of_state(r_nx, db.slot_log2);
                     q_nx = load_slot<CPLX>(db.slots, sl_nx);
+                    if (CPLX) v_nx = load_slot_value(db.slots, sl_nx);
                 }
                 uint64_t key;
                 double vr, vi;
-                if (!resolve_slot<CPLX>(db, q, sl, r, key, vr, vi)) {
+                if (!resolve_slot<CPLX, true>(db, q, sl, r, key, vr, vi, v)) {
                     ++dropped;
                     continue;
                 }
@@ -1247,22 +1251,34 @@ int run_lanczos(const ed_basis *bc, const double *J, const double *Jz, const voi
     const size_t vb = (size_t)nd * 8;
     auto &W = b->lzw;
     const size_t npart = (size_t)std::max(np_apply, vgrid);
-    if (!W.vec[0] || W.cap_steps < n_steps || W.cap_partials < npart) {
+    // the vectors are sized by the basis and kept between calls; only the
+    // coefficient histories grow with n_steps
+    if (!W.vec[0] || W.cap_partials < npart) {
         free_lanczos_workspace(b);
         bool ok = true;
         for (int k = 0; k < 3; ++k) ok = ok && hipMalloc((void **)&W.vec[k], vb) == hipSuccess;
         ok = ok && hipMalloc((void **)&W.partials, npart * 8) == hipSuccess;
-        ok = ok && hipMalloc((void **)&W.ahist, (size_t)n_steps * 8) == hipSuccess;
-        ok = ok && hipMalloc((void **)&W.bhist, (size_t)n_steps * 8) == hipSuccess;
-        ok = ok && hipMalloc((void **)&W.svec, (size_t)n_steps * 8) == hipSuccess;
         ok = ok && hipMalloc(&W.state, sizeof(LzState)) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
             free_lanczos_workspace(b);
             return set_error(ED_ERR_OOM, "Lanczos vectors (3 x %zu bytes)", vb);
         }
-        W.cap_steps = n_steps;
         W.cap_partials = npart;
+    }
+    if (W.cap_steps < n_steps) {
+        for (double **p : {&W.ahist, &W.bhist, &W.svec}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        bool ok = true;
+        for (double **p : {&W.ahist, &W.bhist, &W.svec}) ok = ok && hipMalloc((void **)p, (size_t)n_steps * 8) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            free_lanczos_workspace(b);
+            return set_error(ED_ERR_OOM, "Lanczos coefficient history");
+        }
+        W.cap_steps = n_steps;
     }
     double *A = W.vec[0], *B = W.vec[1], *C = W.vec[2], *partials = W.partials, *ahist = W.ahist, *bhist = W.bhist,
            *svec = W.svec;

@@ -649,13 +649,13 @@ int multi_lanczos(ed_multi *mb, const double *J, const void *v0, int n_steps, do
     auto &W = mb->lzw;
     const size_t vb = (size_t)D * K * 16;
     const size_t npart = (size_t)vgrid * K;
-    if (!W.vec[0] || W.cap_steps < n_steps || W.cap_partials < npart) {
+    // vectors are sized by the basis and kept between calls; only the
+    // coefficient histories grow with n_steps
+    if (!W.vec[0] || W.cap_partials < npart) {
         multi_free_workspace(mb);
         bool ok = true;
         for (int k = 0; k < 2; ++k) ok = ok && hipMalloc(&W.vec[k], vb) == hipSuccess;
         ok = ok && hipMalloc((void **)&W.partials, npart * 8) == hipSuccess;
-        ok = ok && hipMalloc((void **)&W.ahist, (size_t)K * n_steps * 8) == hipSuccess;
-        ok = ok && hipMalloc((void **)&W.bhist, (size_t)K * n_steps * 8) == hipSuccess;
         ok = ok && hipMalloc((void **)&W.sector, (size_t)K * sizeof(MlzSector)) == hipSuccess;
         ok = ok && hipMalloc(&W.state, sizeof(MlzState)) == hipSuccess;
         if (!ok) {
@@ -663,8 +663,21 @@ int multi_lanczos(ed_multi *mb, const double *J, const void *v0, int n_steps, do
             multi_free_workspace(mb);
             return set_error(ED_ERR_OOM, "batched Lanczos vectors (2 x %zu bytes)", vb);
         }
-        W.cap_steps = n_steps;
         W.cap_partials = npart;
+    }
+    if (W.cap_steps < n_steps) {
+        for (double **p : {&W.ahist, &W.bhist}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        bool ok = true;
+        for (double **p : {&W.ahist, &W.bhist}) ok = ok && hipMalloc((void **)p, (size_t)K * n_steps * 8) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            multi_free_workspace(mb);
+            return set_error(ED_ERR_OOM, "batched Lanczos coefficient history");
+        }
+        W.cap_steps = n_steps;
     }
     double2 *A = (double2 *)W.vec[0], *B = (double2 *)W.vec[1];
     MlzSector *sec = (MlzSector *)W.sector;
