@@ -219,7 +219,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="build, then run --hv-reps H.v launches only")
-    ap.add_argument("--batch", type=int, default=18, help="sectors per batched launch (triangular36_allk)")
+    ap.add_argument("--batch", type=int, default=12, help="sectors per batched launch (triangular36_allk)")
     ap.add_argument("--sectors", default="all", choices=["all", "inequivalent"],
                     help="triangular36_allk: all 36 momenta, or the 20 inequivalent ones")
     ap.add_argument("--autotune", action="store_true",

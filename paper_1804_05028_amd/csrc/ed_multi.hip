@@ -173,6 +173,22 @@ __global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
             const uint32_t g = g_nx;
             const double jh = jh_nx;
             ulonglong2 q = q_nx;
+            while (q.x != kEmpty && (q.x & kStateMask) != r) {
+                sl = (sl + 1) & smask;
+                q = load_slot<false>(db.slots, sl);
+            }
+            const bool found = q.x != kEmpty;
+            const uint64_t mij = found ? (mi & (q.y >> 32)) : 0ull;
+            // the target's amplitudes are requested before the next term's
+            // search, which hides their latency
+            constexpr bool kPre = KB <= 16;   // registers allow holding the next row's amplitudes
+            double2 xv[kPre ? KB : 1];
+            if (MODE == 0 && kPre) {
+                const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K;
+#pragma unroll
+                for (int k = 0; k < KB; ++k)
+                    xv[k] = (k < K && ((mij >> k) & 1ull)) ? xj[k] : make_double2(0.0, 0.0);
+            }
             if (term + 1 < n_terms) {
                 const BondLds bd = c.bonds[pop_bond(am)];
                 anti_sum += bd.jzhalf;
@@ -181,15 +197,10 @@ __global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
                 sl_nx = slot_of_state(r_nx, db.slot_log2);
                 q_nx = load_slot<false>(db.slots, sl_nx);
             }
-            while (q.x != kEmpty && (q.x & kStateMask) != r) {
-                sl = (sl + 1) & smask;
-                q = load_slot<false>(db.slots, sl);
-            }
-            if (q.x == kEmpty) {
+            if (!found) {
                 dropped += 1.0;
                 continue;
             }
-            const uint64_t mij = mi & (q.y >> 32);
             if (MODE == 1) {
                 shared += 1.0;
 #pragma unroll
@@ -197,15 +208,26 @@ __global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
                 continue;
             }
             const double amp = jh * rs_i * c.div_sqrt[q.x >> kNormShift];
-            const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K;
             const double2 *ch = chik + (size_t)g * K;
+            if (kPre) {
 #pragma unroll
-            for (int k = 0; k < KB; ++k) {
-                if (k < K && ((mij >> k) & 1ull)) {
-                    const double2 xv = xj[k];
-                    const double2 cv = ch[k];
-                    ar[k] += amp * (cv.x * xv.x - cv.y * xv.y);
-                    ai[k] += amp * (cv.x * xv.y + cv.y * xv.x);
+                for (int k = 0; k < (kPre ? KB : 1); ++k) {
+                    if (k < K) {
+                        const double2 cv = ch[k];
+                        ar[k] += amp * (cv.x * xv[k].x - cv.y * xv[k].y);
+                        ai[k] += amp * (cv.x * xv[k].y + cv.y * xv[k].x);
+                    }
+                }
+            } else {
+                const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K;
+#pragma unroll
+                for (int k = 0; k < KB; ++k) {
+                    if (k < K && ((mij >> k) & 1ull)) {
+                        const double2 xw = xj[k];
+                        const double2 cv = ch[k];
+                        ar[k] += amp * (cv.x * xw.x - cv.y * xw.y);
+                        ai[k] += amp * (cv.x * xw.y + cv.y * xw.x);
+                    }
                 }
             }
         }
