@@ -69,6 +69,30 @@ def measured_traffic(key):
     return rec[1] + rec[2] if kernel_digest() == rec[0] else None
 
 
+AUTOTUNE_NSUB = {"square40_j1j2": [4, 5], "square40_j1j2j3": [4, 5], "triangular36": [3, 4], "square32_disorder": [4, 8], "square16": [2, 4]}
+
+
+def _workload(name, n_sub):
+    from ed_inputs import workloads as wl
+    if name == "square40_j1j2":
+        return wl.square_40_j1j2(n_sub=n_sub or 4), "J1-J2 square 40 (6,2)x(-2,6), 40T x C4 x flip, Gamma.A.even, Sz=0"
+    if name == "square40_j1j2j3":
+        return (wl.square_40_j1j2j3(n_sub=n_sub or 4),
+                "J1-J2-J3 square 40 (6,2)x(-2,6), J2=0.5 J3=0.25, 40T x C4 x flip, Gamma.A.even, Sz=0")
+    if name == "triangular36":
+        return wl.triangular_36(n_sub=n_sub or 4), "Heisenberg triangular 36 (6,0)x(0,6), 36T x C6v x flip, Gamma.A1.even, Sz=0"
+    if name == "square32_disorder":
+        from ed_inputs import lattice as lat
+        w = wl.square_32_disorder(n_sub=n_sub or 4)
+        # the translation sector of a disordered H is that of its orbit-averaged couplings
+        w = wl.Workload(w.name, w.cluster, w.chi, w.n_up, lat.orbit_mean(w.J, lat.bond_orbits(w.cluster)),
+                        w.description)
+        return w, "Heisenberg square 32 (4,4)x(-4,4), 32T, k=0, orbit-averaged J_b ~ U(0.8,1.2)"
+    if name == "square16":
+        return wl.square_4x4(n_sub=n_sub or 4), "Heisenberg square 16 (4x4), 16T, k=0, Sz=0"
+    raise SystemExit(f"unknown workload {name}")
+
+
 def _allk_workloads(n_sub, which="all"):
     """Momentum sectors of the 36-site triangular cluster with translations
     only: all 36, or the 20 inequivalent ones (Gamma, the three M points and
@@ -222,6 +246,8 @@ def main():
     ap.add_argument("--batch", type=int, default=12, help="sectors per batched launch (triangular36_allk)")
     ap.add_argument("--sectors", default="all", choices=["all", "inequivalent"],
                     help="triangular36_allk: all 36 momenta, or the 20 inequivalent ones")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the adjoint (dL/dx = H gy and the per-bond sums) on the same basis")
     ap.add_argument("--autotune", action="store_true",
                     help="search sublattice decompositions and launch tunings first, then bench the fastest")
     args = ap.parse_args()
@@ -291,6 +317,22 @@ def main():
         print(json.dumps({"hv_ms": hv_ms, "terms": terms, "D": D, "copy_bytes_each_way": D * x.element_size()}))
         return
 
+    adjoint = None
+    if args.adjoint:
+        gy = torch.randn(D, dtype=dt, device="cuda", generator=gen)
+        basis.backward(J, x, gy)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.hv_reps):
+            basis.backward(J, x, gy)          # gx = H gy and gJ_b (synchronises)
+        full_ms = (time.perf_counter() - t0) * 1e3 / args.hv_reps
+        t0 = time.perf_counter()
+        for _ in range(args.hv_reps):
+            basis.backward(J, x, gy, want_gx=False)
+        gj_ms = (time.perf_counter() - t0) * 1e3 / args.hv_reps
+        adjoint = {"backward_ms": full_ms, "per_bond_sums_ms": gj_ms, "n_bonds": int(basis.n_bonds)}
+        print(f"[bench] adjoint {full_ms:.2f} ms (per-bond sums {gj_ms:.2f} ms)", file=sys.stderr, flush=True)
+
     # ---- Lanczos steps ----------------------------------------------------------
     if args.warmup > 0:
         basis.lanczos(J, x, args.warmup)
@@ -346,6 +388,8 @@ def main():
     }
     if tuned is not None:
         out["autotune"] = tuned
+    if adjoint is not None:
+        out["adjoint"] = adjoint
     print(json.dumps(out))
     _ = math
 
