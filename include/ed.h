@@ -17,6 +17,11 @@
  *  - stream is a hipStream_t passed as void* (NULL = the default stream).
  *    Calls that only enqueue work return once it is enqueued; calls that
  *    return host results synchronise the stream first.
+ *  - A handle keeps per-call state on the device (the couplings written
+ *    into its tables, the input amplitudes scattered into its index, the
+ *    Lanczos workspace), so calls on one handle must not overlap: use it
+ *    from one thread and one stream at a time.  Different handles are
+ *    independent.
  *  - Spin configurations are uint64 codes: site s <-> bit (N-1-s), so site 0
  *    is the most significant bit, and up = 1 (sec. "Symmetry adapted basis
  *    states"; the worked examples' integers (011)_2 = 3 fix this order).
