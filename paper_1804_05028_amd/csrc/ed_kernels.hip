@@ -207,19 +207,22 @@ __global__ void k_pack_cplx(const double2 *x, const uint32_t *slot_of, char *slo
 // blocks in fixed order: the result is deterministic.
 // ---------------------------------------------------------------------------
 
-template <bool CPLX, typename AT, int INDEX>
+template <bool CPLX, typename AT, int INDEX, int NSC>
 __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, const typename Scalar<CPLX>::T *__restrict__ x,
                                                      const typename Scalar<CPLX>::T *__restrict__ gy,
-                                                     double *partials /* [grid][nb] */)
+                                                     double *partials /* [grid][nb + 1] */)
 {
+    // A_b = 1/4 sum_i Re(conj(gy_i) x_i)                      (every bond parallel)
+    //     + sum_{i: b antiparallel} [ -1/2 Re(conj(gy_i) x_i) + Re(conj(gy_i) t_b(i)) ]
+    // where t_b(i) is the flip term of bond b in row i.  Column nb of the
+    // partials carries the bond-independent sum, added on the host.  Wave
+    // sums are held by lane b % 64 in registers; blocks reduce in fixed order.
     extern __shared__ __align__(16) char lds[];
     const Ctx<AT> c = stage<AT>(dm, lds);
     const int nb = dm.nb;
     const int nwaves = blockDim.x / kWave;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    double *acc = (double *)(lds + dm.lds_total);   // [nwaves][nb]
-    for (int k = threadIdx.x; k < nwaves * nb; k += blockDim.x) acc[k] = 0.0;
-    __syncthreads();
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, tot = 0.0;
     const int64_t D = db.dim;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t wave_first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane;
@@ -243,14 +246,21 @@ __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, c
                 gx_r = g_r * *(const double *)&x[i];
             }
         }
+        tot += wave_sum(gx_r);
         for (int b = 0; b < nb; ++b) {
             const BondLds bd = c.bonds[b];
             const uint64_t t = s & bd.mask;
             const bool anti = valid && (t != 0) && (t != bd.mask);
-            double contrib = valid ? (anti ? -0.25 : 0.25) * gx_r : 0.0;
+            if (!__ballot(anti)) continue;   // no row of this wave flips bond b
+            double contrib = 0.0;
             if (anti) {
-                uint32_t g, mval;
-                const uint64_t r = find_rep(c, s ^ bd.mask, g, mval);
+                contrib = -0.5 * gx_r;
+                uint32_t g, mval = 0;
+                uint64_t r;
+                if (INDEX == IDX_HASH)
+                    r = rep_search<AT, NSC>(c, s ^ bd.mask, g);
+                else
+                    r = find_rep(c, s ^ bd.mask, g, mval);
                 double cr, ci;
                 chi_of<CPLX>(c, g, cr, ci);
                 bool found = false;
@@ -284,14 +294,29 @@ __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, c
                 }
             }
             const double wsum = wave_sum(contrib);
-            if (lane == 0) acc[wave * nb + b] += wsum;
+            if (lane == (b & (kWave - 1))) {
+                const int q = b >> 6;
+                if (q == 0) a0 += wsum;
+                else if (q == 1) a1 += wsum;
+                else if (q == 2) a2 += wsum;
+                else a3 += wsum;
+            }
         }
     }
+    // block reduction in fixed order (the tables are no longer needed)
     __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        double tot = 0.0;
-        for (int w = 0; w < nwaves; ++w) tot += acc[w * nb + b];
-        partials[(size_t)blockIdx.x * nb + b] = tot;
+    double *red = (double *)lds;   // [nwaves][nb + 1]
+    const int w1 = nb + 1;
+    for (int b = lane; b < nb; b += kWave) {
+        const int q = b >> 6;
+        red[wave * w1 + b] = q == 0 ? a0 : q == 1 ? a1 : q == 2 ? a2 : a3;
+    }
+    if (lane == 0) red[wave * w1 + nb] = tot;
+    __syncthreads();
+    for (int b = threadIdx.x; b < w1; b += blockDim.x) {
+        double sum = 0.0;
+        for (int w = 0; w < nwaves; ++w) sum += red[w * w1 + b];
+        partials[(size_t)blockIdx.x * w1 + b] = sum;
     }
 }
 
@@ -1141,34 +1166,33 @@ int launch_apply(const ed_basis *b, const double *J, const double *Jz, const voi
 
 // ---- adjoint ---------------------------------------------------------------
 
-template <bool CPLX, typename AT, int INDEX>
+template <bool CPLX, typename AT, int INDEX, int NSC>
 static int backward_impl(const ed_basis *b, const void *x, const void *gy, double *gJ_host, hipStream_t st)
 {
     using T = typename Scalar<CPLX>::T;
-    auto kern = k_backward_J<CPLX, AT, INDEX>;
+    auto kern = k_backward_J<CPLX, AT, INDEX, NSC>;
     const int nb = b->t.nb;
-    const int threads = 256;
-    const size_t lds = (size_t)b->dm.lds_total + (size_t)(threads / kWave) * nb * 8;
-    int per_cu = 1;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
-    per_cu = std::max(per_cu, 1);
-    int grid = (int)std::min<int64_t>((b->db.dim + threads - 1) / threads, (int64_t)per_cu * num_cus());
-    grid = std::max(grid, 1);
+    int grid, threads;
+    launch_cfg(b, kern, b->dm.lds_total, &grid, &threads);
+    // the block reduction reuses the table area: [waves][nb + 1] doubles
+    const size_t lds = std::max((size_t)b->dm.lds_total, (size_t)(threads / kWave) * (nb + 1) * 8);
     double *partials = nullptr, *out = nullptr;
-    if (hipMalloc((void **)&partials, (size_t)grid * nb * 8) != hipSuccess ||
-        hipMalloc((void **)&out, (size_t)nb * 8) != hipSuccess) {
+    if (hipMalloc((void **)&partials, (size_t)grid * (nb + 1) * 8) != hipSuccess ||
+        hipMalloc((void **)&out, (size_t)(nb + 1) * 8) != hipSuccess) {
         (void)hipGetLastError();
         if (partials) (void)hipFree(partials);
         return set_error(ED_ERR_OOM, "adjoint partials");
     }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, b->dm, b->db, (const T *)x, (const T *)gy, partials);
-    hipLaunchKernelGGL(k_sum_partials_cols, dim3((nb + 255) / 256), dim3(256), 0, st, (const double *)partials, grid, nb,
-                       out);
-    hipError_t e = hipMemcpyAsync(gJ_host, out, (size_t)nb * 8, hipMemcpyDeviceToHost, st);
+    hipLaunchKernelGGL(k_sum_partials_cols, dim3((nb + 256) / 256), dim3(256), 0, st, (const double *)partials, grid,
+                       nb + 1, out);
+    std::vector<double> h((size_t)nb + 1);
+    hipError_t e = hipMemcpyAsync(h.data(), out, (size_t)(nb + 1) * 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(partials);
     (void)hipFree(out);
     if (e != hipSuccess) return set_error(ED_ERR_HIP, "adjoint failed: %s", hipGetErrorString(e));
+    for (int k = 0; k < nb; ++k) gJ_host[k] = h[k] + 0.25 * h[nb];
     return ED_OK;
 }
 
@@ -1188,20 +1212,20 @@ int launch_backward_J(const ed_basis *b, const double *J, const void *x, const v
     if (rc) return rc;
     const bool c = b->dm.is_complex;
     const int ix = b->db.index_mode, w = b->dm.act_bytes;
-#define ED_CASE(C, A, I) \
-    if (c == C && w == (int)sizeof(A) && ix == I) return backward_impl<C, A, I>(b, x, gy, gJ_host, st);
-    ED_CASE(false, uint8_t, IDX_HASH)
-    ED_CASE(false, uint16_t, IDX_HASH)
-    ED_CASE(false, uint32_t, IDX_HASH)
-    ED_CASE(true, uint8_t, IDX_HASH)
-    ED_CASE(true, uint16_t, IDX_HASH)
-    ED_CASE(true, uint32_t, IDX_HASH)
-    ED_CASE(false, uint8_t, IDX_LIMITS)
-    ED_CASE(false, uint16_t, IDX_LIMITS)
-    ED_CASE(false, uint32_t, IDX_LIMITS)
-    ED_CASE(true, uint8_t, IDX_LIMITS)
-    ED_CASE(true, uint16_t, IDX_LIMITS)
-    ED_CASE(true, uint32_t, IDX_LIMITS)
+    // four sublattices with one to three chunks: search loops fixed at compile time
+    const int nsc = (ix == IDX_HASH && b->dm.ns == 4 && b->dm.n_chunks <= 3) ? 32 + b->dm.n_chunks : 0;
+#define ED_CASE(C, A, I, K) \
+    if (c == C && w == (int)sizeof(A) && ix == I && nsc == K) return backward_impl<C, A, I, K>(b, x, gy, gJ_host, st);
+#define ED_CASES(C, A) \
+    ED_CASE(C, A, IDX_HASH, 0) ED_CASE(C, A, IDX_HASH, 33) ED_CASE(C, A, IDX_HASH, 34) ED_CASE(C, A, IDX_HASH, 35) \
+    ED_CASE(C, A, IDX_LIMITS, 0)
+    ED_CASES(false, uint8_t)
+    ED_CASES(false, uint16_t)
+    ED_CASES(false, uint32_t)
+    ED_CASES(true, uint8_t)
+    ED_CASES(true, uint16_t)
+    ED_CASES(true, uint32_t)
+#undef ED_CASES
 #undef ED_CASE
     return set_error(ED_ERR_ARG, "no kernel variant");
 }
