@@ -1105,14 +1105,14 @@ static int apply_ns(const ed_basis *b, const void *x, void *y, const void *vprev
 {
 #define ED_NS(K) \
     case K: return apply_impl<CPLX, AT, IDX_HASH, MODE, K * 8>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    // four sublattices with one to three chunks: chunk count fixed too
+    if (b->dm.ns == 4 && b->dm.n_chunks == 1)
+        return apply_impl<CPLX, AT, IDX_HASH, MODE, 33>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    if (b->dm.ns == 4 && b->dm.n_chunks == 2)
+        return apply_impl<CPLX, AT, IDX_HASH, MODE, 34>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    if (b->dm.ns == 4 && b->dm.n_chunks == 3)
+        return apply_impl<CPLX, AT, IDX_HASH, MODE, 35>(b, x, y, vprev, partials, stats, lz, jsq, st);
     if (MODE != 1) {
-        // four sublattices with one to three chunks: chunk count fixed too
-        if (b->dm.ns == 4 && b->dm.n_chunks == 1)
-            return apply_impl<CPLX, AT, IDX_HASH, MODE, 33>(b, x, y, vprev, partials, stats, lz, jsq, st);
-        if (b->dm.ns == 4 && b->dm.n_chunks == 2)
-            return apply_impl<CPLX, AT, IDX_HASH, MODE, 34>(b, x, y, vprev, partials, stats, lz, jsq, st);
-        if (b->dm.ns == 4 && b->dm.n_chunks == 3)
-            return apply_impl<CPLX, AT, IDX_HASH, MODE, 35>(b, x, y, vprev, partials, stats, lz, jsq, st);
         switch (b->dm.ns) {
             ED_NS(2) ED_NS(3) ED_NS(4) ED_NS(5) ED_NS(6) ED_NS(8) ED_NS(9) ED_NS(10)
         default: break;
