@@ -17,7 +17,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -391,7 +390,6 @@ def main():
     if adjoint is not None:
         out["adjoint"] = adjoint
     print(json.dumps(out))
-    _ = math
 
 
 if __name__ == "__main__":

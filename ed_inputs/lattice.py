@@ -234,7 +234,6 @@ def build_cluster(name, L1, L2, bond_vectors, point_group_gens=(), spin_flip=Fal
 def _hnf(M1, M2):
     """Hermite normal form ((a, 0), (b, d)), a, d > 0, 0 <= b < a, of the
     lattice spanned by M1, M2 (the unique basis of that shape)."""
-    import math
     # column operations on [M1 M2] (2x2 integer) to lower-triangular form
     (x1, y1), (x2, y2) = M1, M2
     # make the second coordinate of the first vector 0 by the Euclidean algorithm on y
@@ -248,7 +247,6 @@ def _hnf(M1, M2):
     if d < 0:
         b, d = -b, -d
     b %= a
-    _ = math
     return ((a, 0), (b, d))
 
 

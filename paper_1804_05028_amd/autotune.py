@@ -112,4 +112,4 @@ def speedup_table(results):
     return [(r["n_sub"], r["tuning"], r["hv_ms"], r["hv_ms"] / b) for r in timed]
 
 
-__all__ = ["autotune", "default_candidates", "speedup_table"]
+__all__ = ["autotune", "autotune_decompositions", "default_candidates", "speedup_table"]

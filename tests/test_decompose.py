@@ -1,7 +1,5 @@
 """Sublattice decompositions: enumeration of the stable superlattices and
 their ranking by estimated representative-search cost (host only)."""
-import itertools
-
 import numpy as np
 import pytest
 
@@ -66,7 +64,6 @@ def test_hnf_is_a_lattice_invariant():
             v1 = (U[0, 0] * a[0] + U[0, 1] * b[0], U[0, 0] * a[1] + U[0, 1] * b[1])
             v2 = (U[1, 0] * a[0] + U[1, 1] * b[0], U[1, 0] * a[1] + U[1, 1] * b[1])
             assert lat._hnf(v1, v2) == lat._hnf(*M)
-    _ = itertools
 
 
 def test_ranking_prefers_four_sublattices_on_the_large_clusters():

@@ -5,7 +5,6 @@ pins (worked examples, closed-form energies, definition-level matrix,
 character-formula dimensions) are then run against it.  This runs on the CPU
 only and never touches the product library.
 """
-import ctypes
 import math
 import os
 import subprocess
@@ -123,4 +122,3 @@ def test_mutant_is_caught(tmp_path, name, monkeypatch):
         assert not _pins_pass(), f"planted mistake '{name}' passed every pin"
     finally:
         bf._lib = saved
-    _ = ctypes

@@ -70,12 +70,10 @@ def _xxz_cases():
     out.append(("ring8_k1", c8, lat.characters(c8, 1), 4, np.ones(8), 0.5 * np.ones(8)))
     ct = lat.triangular((2, 2), (-2, 4), spin_flip=True)
     out.append(("tri12_A1", ct, lat.characters(ct, 0), 6, np.ones(ct.n_bonds), 2.0 * np.ones(ct.n_bonds)))
-    w = wl.square_4x4()
     c = lat.square((4, 0), (0, 4), j2=True, j3=True, rotations=False, superlattice=wl.SQ_2X2, name="sq16j3")
     J = np.array([1.0, 0.5, 0.25])[c.bond_kind]
     out.append(("sq16_j1j2j3_k3", c, lat.characters(c, 3), 8, J, J))
     out.append(("sq16_j1j2j3_xxz", c, lat.characters(c, 0), 7, J, 1.5 * J))
-    _ = w
     return out
 
 
