@@ -102,7 +102,17 @@ typedef struct {
     int32_t hash_load_pct;  /* index_mode 0: maximum load factor of the slot table in percent (10..90)   */
     int32_t table_entry_bytes; /* 1, 2 or 4 bytes per symmetry-action entry (wide ones carry the block
                                   position); 0 = automatic                                              */
+    int32_t search_mode;    /* representative search of the index_mode 0 H.v and Lanczos kernels
+                               (the batched and adjoint kernels always run the one-stage search):
+                               ED_SEARCH_ONE_STAGE = assemble the full image of every candidate;
+                               ED_SEARCH_TWO_STAGE = image the block landing below the top block
+                               first and assemble only the candidates minimising it (2 to 4
+                               sublattices, else ED_ERR_UNSUPPORTED); 0 = two-stage when a host
+                               sample of the search averages at least 3 candidates               */
 } ed_tuning_t;
+
+#define ED_SEARCH_ONE_STAGE 1
+#define ED_SEARCH_TWO_STAGE 2
 
 typedef struct ed_tables ed_tables_t;   /* host-side sublattice-coding tables */
 typedef struct ed_basis ed_basis_t;     /* device-resident sector basis       */
@@ -129,6 +139,9 @@ typedef struct {
     int32_t lds_bytes;          /* LDS bytes of the staged tables per block    */
     int64_t device_bytes;       /* device memory owned by the handle           */
     double build_ms;            /* wall time of ed_build_basis                 */
+    int32_t search_mode;        /* search of the H.v kernels: ED_SEARCH_ONE_STAGE or _TWO_STAGE */
+    double mean_candidates;     /* candidate symmetries per search, host Alg. 2 on 2048 random
+                                   configurations at this n_up                  */
 } ed_basis_info_t;
 
 /* Library version string (static). */

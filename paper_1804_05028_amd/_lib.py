@@ -46,7 +46,11 @@ class ed_tuning_t(ctypes.Structure):
     _fields_ = [("limits_bits", ctypes.c_int32), ("index_mode", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("chunk_bits", ctypes.c_int32), ("hash_load_pct", ctypes.c_int32),
-                ("table_entry_bytes", ctypes.c_int32)]
+                ("table_entry_bytes", ctypes.c_int32), ("search_mode", ctypes.c_int32)]
+
+
+ED_SEARCH_ONE_STAGE = 1
+ED_SEARCH_TWO_STAGE = 2
 
 
 class ed_tables_info_t(ctypes.Structure):
@@ -63,7 +67,8 @@ class ed_basis_info_t(ctypes.Structure):
                 ("limits_bits", ctypes.c_int32), ("n_keys", ctypes.c_int64), ("n_slots", ctypes.c_int64),
                 ("chunk_bits", ctypes.c_int32), ("table_entry_bytes", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double)]
+                ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double), ("search_mode", ctypes.c_int32),
+                ("mean_candidates", ctypes.c_double)]
 
 
 class ed_multi_info_t(ctypes.Structure):
@@ -240,7 +245,7 @@ def _tuning(tuning):
     return ed_tuning_t(int(tuning.get("limits_bits", 0)), int(tuning.get("index_mode", 0)),
                        int(tuning.get("block_threads", 0)), int(tuning.get("blocks_per_cu", 0)),
                        int(tuning.get("chunk_bits", 0)), int(tuning.get("hash_load_pct", 0)),
-                       int(tuning.get("table_entry_bytes", 0)))
+                       int(tuning.get("table_entry_bytes", 0)), int(tuning.get("search_mode", 0)))
 
 
 def ed_build_basis(arrays: ModelArrays, n_up, tuning=None, stream=None):

@@ -2,7 +2,7 @@
 
 For each sublattice decomposition offered by the caller and each candidate
 tuning (action-table chunk width and entry width, threads per block, blocks
-per compute unit), build the basis, time a few H.v launches with HIP events
+per compute unit, one- or two-stage representative search), build the basis, time a few H.v launches with HIP events
 on the current stream, and keep the fastest.  Configurations the library
 rejects (tables that do not fit in LDS, unsupported entry widths) are
 recorded and skipped.  Every candidate computes the same H.v; only its speed
@@ -28,6 +28,9 @@ def default_candidates(sub_bits):
     out.append({"block_threads": 512})
     if sub_bits <= 8:
         out.append({"table_entry_bytes": 1})
+    # both representative searches (the automatic choice is one of them)
+    out.append({"search_mode": L.ED_SEARCH_ONE_STAGE})
+    out.append({"search_mode": L.ED_SEARCH_TWO_STAGE})
     return out
 
 

@@ -105,6 +105,40 @@ int ed_tables_find_rep(const ed_tables_t *tt, int64_t n, const uint64_t *states,
     return ED_OK;
 }
 
+// Mean number of candidate symmetries of the host search (Alg. "Sublattice
+// coding algorithm for finding the representative") over 2048 configurations
+// with n_up up spins, drawn from a fixed splitmix64 stream.
+static double sample_mean_candidates(const ed::Tables &t, int n_up)
+{
+    if (n_up <= 0 || n_up >= t.N) return 1.0;
+    uint64_t z = 0x2545F4914F6CDD1Dull;
+    auto next = [&z]() {
+        uint64_t x = (z += 0x9E3779B97F4A7C15ull);
+        x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+        x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+        return x ^ (x >> 31);
+    };
+    const int n_samples = 2048;
+    std::vector<int> sites(t.N);
+    double total = 0.0;
+    for (int k = 0; k < n_samples; ++k) {
+        for (int i = 0; i < t.N; ++i) sites[i] = i;
+        uint64_t s = 0;
+        for (int i = 0; i < n_up; ++i) {   // partial Fisher-Yates: n_up distinct sites
+            const int j = i + (int)(next() % (uint64_t)(t.N - i));
+            std::swap(sites[i], sites[j]);
+            s |= 1ull << (t.N - 1 - sites[i]);
+        }
+        int g = 0, nc = 0;
+        (void)t.find_rep(s, &g, &nc);
+        total += nc;
+    }
+    return total / n_samples;
+}
+
+// two-stage search by default from this mean candidate count on
+static constexpr double kTwoStageMinCandidates = 3.0;
+
 static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irrep_t *irrep, int32_t n_up,
                               const ed_tuning_t *tuning, uint32_t lds_reserve, void *stream, ed_basis_t **out)
 {
@@ -133,7 +167,8 @@ static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, co
     if (b->tuning.index_mode < 0 || b->tuning.index_mode > 1 || b->tuning.chunk_bits < 0 ||
         b->tuning.chunk_bits > 16 || b->tuning.hash_load_pct < 0 || b->tuning.hash_load_pct > 90 ||
         (b->tuning.table_entry_bytes != 0 && b->tuning.table_entry_bytes != 1 && b->tuning.table_entry_bytes != 2 &&
-         b->tuning.table_entry_bytes != 4)) {
+         b->tuning.table_entry_bytes != 4) ||
+        b->tuning.search_mode < 0 || b->tuning.search_mode > ED_SEARCH_TWO_STAGE) {
         delete b;
         return set_error(ED_ERR_ARG, "tuning fields out of range");
     }
@@ -162,6 +197,14 @@ static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, co
     dm.is_complex = cplx ? 1 : 0;
     dm.trivial_irrep = trivial ? 1 : 0;
     dm.n_div = (int)b->divs.size();
+    b->mean_candidates = sample_mean_candidates(t, n_up);
+    const bool two_stage_ok = t.ns >= 2 && t.ns <= 4;
+    if (b->tuning.search_mode == ED_SEARCH_TWO_STAGE && !two_stage_ok) {
+        delete b;
+        return set_error(ED_ERR_UNSUPPORTED, "the two-stage search needs 2 to 4 sublattices (%d)", t.ns);
+    }
+    b->staged = two_stage_ok && (b->tuning.search_mode == ED_SEARCH_TWO_STAGE ||
+                                 (b->tuning.search_mode == 0 && b->mean_candidates >= kTwoStageMinCandidates));
     rc = ed::launch_basis_build(b, stream);
     if (rc) {
         ed_free_basis(b);
@@ -212,6 +255,8 @@ int ed_basis_info(const ed_basis_t *b, ed_basis_info_t *info)
     info->lds_bytes = (int32_t)b->dm.lds_total;
     info->device_bytes = b->device_bytes;
     info->build_ms = b->build_ms;
+    info->search_mode = b->staged ? ED_SEARCH_TWO_STAGE : ED_SEARCH_ONE_STAGE;
+    info->mean_candidates = b->mean_candidates;
     return ED_OK;
 }
 

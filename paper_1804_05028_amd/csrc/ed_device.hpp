@@ -238,12 +238,141 @@ __device__ __forceinline__ uint64_t find_rep_ns(const Ctx<AT> &c, uint64_t s, ui
     return best;
 }
 
+// The same search in two stages, for groups with many candidates per search.
+// Every candidate's top block is MinRep, so the image order is decided first
+// by the block landing at position 1.  Stage 1 images only that block for
+// every candidate of a Sym list (one table entry chunk per chunk instead of
+// all blocks) and keeps the candidates attaining its minimum in a bit mask;
+// stage 2 assembles the full image of those few.  The minimum and the
+// minimiser chosen (the first in list order) are those of find_rep_ns.
+// Lists longer than 64 candidates take the one-stage loop.
+template <typename AT, int NS, int NC>
+__device__ __forceinline__ uint64_t find_rep_staged(const Ctx<AT> &c, uint64_t s, uint32_t &g_best)
+{
+    static_assert(NS >= 2 && NS <= 4, "two-stage search for 2 to 4 sublattices");
+    const int N = c.N, m = c.m, cb = c.cb;
+    const int nc = NC > 0 ? NC : c.nc;
+    const uint32_t P = c.mmask + 1;
+    uint32_t sx[NS];
+    uint32_t minr = 0xFFFFFFFFu;
+#pragma unroll
+    for (int X = 0; X < NS; ++X) {
+        sx[X] = (uint32_t)(s >> (N - (X + 1) * m)) & c.mmask;
+        minr = min(minr, c.rep[X * P + sx[X]] & 0xFFFFu);
+    }
+    uint32_t tie = 0;
+#pragma unroll
+    for (int X = 0; X < NS; ++X) tie |= (uint32_t)((c.rep[X * P + sx[X]] & 0xFFFFu) == minr) << X;
+    const uint64_t top = (uint64_t)minr << (N - m);
+    const uint32_t sh1 = (uint32_t)(N - 2 * m);   // shift of the block at position 1
+    constexpr uint32_t kImgMask = ActTraits<AT>::kPos ? (1u << ActTraits<AT>::kPosShift) - 1u : 0xFFFFFFFFu;
+    uint64_t best = ~0ull;
+    uint32_t bg = 0;
+    // full image of candidate entry ent
+    auto full_image = [&](uint32_t ent) -> uint64_t {
+        const uint32_t u = (ent >> 16) & 0x7FFFu;
+        const AT *tu = c.act + ((size_t)u * NS * nc << cb);
+        uint64_t v = 0;
+#pragma unroll
+        for (int X = 0; X < NS; ++X) {
+            const AT *t = tu + ((X * nc) << cb);
+            uint32_t blk = 0;
+            if (NC > 0) {
+#pragma unroll
+                for (int k2 = 0; k2 < (NC > 0 ? NC : 1); ++k2) blk |= t[(k2 << cb) | ((sx[X] >> (k2 * cb)) & c.cmask)];
+            } else {
+                for (int k2 = 0; k2 < nc; ++k2) blk |= t[(k2 << cb) | ((sx[X] >> (k2 * cb)) & c.cmask)];
+            }
+            v |= place_block(c, u, NS, X, blk);
+        }
+        return ((v ^ ((ent >> 31) ? ~0ull : 0ull)) & c.low_mask) | top;
+    };
+    while (tie) {
+        const int Y = __builtin_ctz(tie);
+        tie &= tie - 1;
+        const uint32_t sy = (uint32_t)(s >> (N - (Y + 1) * m)) & c.mmask;
+        const uint32_t off = c.rep[Y * P + sy] >> 16;
+        const uint32_t cnt = c.sym[off];
+        if (cnt > 64) {
+            for (uint32_t k = 1; k <= cnt; ++k) {
+                const uint32_t ent = c.sym[off + k];
+                const uint64_t v = full_image(ent);
+                if (v < best) {
+                    best = v;
+                    bg = ent & 0xFFFFu;
+                }
+            }
+            continue;
+        }
+        // stage 1: the position-1 block of every candidate
+        uint32_t min1 = 0xFFFFFFFFu;
+        uint64_t keep = 0;
+        for (uint32_t k = 0; k < cnt; ++k) {
+            const uint32_t ent = c.sym[off + 1 + k];
+            const uint32_t u = (ent >> 16) & 0x7FFFu;
+            // the source block landing at position 1 (block shifts of u: one
+            // byte per source block; four of them form one aligned word)
+            uint32_t src = 0, sxs = sx[0];
+            if constexpr (NS == 4) {
+                const uint32_t shw = *(const uint32_t *)(c.shift + u * NS);
+#pragma unroll
+                for (int X = 1; X < NS; ++X)
+                    if (((shw >> (8 * X)) & 0xFFu) == sh1) {
+                        src = X;
+                        sxs = sx[X];
+                    }
+            } else {
+#pragma unroll
+                for (int X = 1; X < NS; ++X)
+                    if (c.shift[u * NS + X] == sh1) {
+                        src = X;
+                        sxs = sx[X];
+                    }
+            }
+            const AT *t = c.act + (((size_t)u * NS + src) * nc << cb);
+            uint32_t blk = 0;
+            if (NC > 0) {
+#pragma unroll
+                for (int k2 = 0; k2 < (NC > 0 ? NC : 1); ++k2) blk |= t[(k2 << cb) | ((sxs >> (k2 * cb)) & c.cmask)];
+            } else {
+                for (int k2 = 0; k2 < nc; ++k2) blk |= t[(k2 << cb) | ((sxs >> (k2 * cb)) & c.cmask)];
+            }
+            blk &= kImgMask;
+            if (ent >> 31) blk ^= c.mmask;
+            if (blk < min1) {
+                min1 = blk;
+                keep = 1ull << k;
+            } else if (blk == min1) {
+                keep |= 1ull << k;
+            }
+        }
+        // stage 2: full images of the survivors, in list order
+        while (keep) {
+            const int k = __builtin_ctzll(keep);
+            keep &= keep - 1;
+            const uint32_t ent = c.sym[off + 1 + k];
+            const uint64_t v = full_image(ent);
+            if (v < best) {
+                best = v;
+                bg = ent & 0xFFFFu;
+            }
+        }
+    }
+    g_best = bg;
+    return best;
+}
+
+constexpr int kStagedFlag = 128;   // NSC bit selecting the two-stage search
+
 // NSC = NS * 8 + NC: sublattices and chunks fixed at compile time (0 = read
-// them at run time; NC = 0 with NS > 0 fixes only the sublattice count)
+// them at run time; NC = 0 with NS > 0 fixes only the sublattice count);
+// NSC + kStagedFlag selects the two-stage search (2 to 4 sublattices)
 template <typename AT, int NSC>
 __device__ __forceinline__ uint64_t rep_search(const Ctx<AT> &c, uint64_t s, uint32_t &g)
 {
-    constexpr int NS = NSC / 8, NC = NSC % 8;
+    constexpr int NS = (NSC & 127) / 8, NC = NSC % 8;
+    constexpr bool STAGED = (NSC & kStagedFlag) != 0;
+    if constexpr (STAGED) return find_rep_staged<AT, (NS >= 2 && NS <= 4 ? NS : 4), NC>(c, s, g);
     if (NS > 0) return find_rep_ns<AT, (NS > 0 ? NS : 1), NC>(c, s, g);
     uint32_t mv;
     return find_rep(c, s, g, mv);

@@ -122,6 +122,8 @@ struct ed_basis {
     int64_t n_slots = 0;
     std::vector<double> J_cache;   // couplings currently written into the blob
     uint32_t lds_reserve = 0;      // LDS bytes kept free for kernels that stage more
+    double mean_candidates = 0.0;  // host Alg. 2 on random configurations
+    int staged = 0;                // the H.v kernels run the two-stage search
     // Lanczos workspace, kept between calls and freed with the handle
     struct {
         double *vec[3] = {nullptr, nullptr, nullptr};

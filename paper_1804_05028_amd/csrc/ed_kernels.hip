@@ -1105,6 +1105,20 @@ static int apply_ns(const ed_basis *b, const void *x, void *y, const void *vprev
 {
 #define ED_NS(K) \
     case K: return apply_impl<CPLX, AT, IDX_HASH, MODE, K * 8>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    if (b->staged) {
+        constexpr int F = kStagedFlag;
+        if (b->dm.ns == 4 && b->dm.n_chunks == 1)
+            return apply_impl<CPLX, AT, IDX_HASH, MODE, 33 + F>(b, x, y, vprev, partials, stats, lz, jsq, st);
+        if (b->dm.ns == 4 && b->dm.n_chunks == 2)
+            return apply_impl<CPLX, AT, IDX_HASH, MODE, 34 + F>(b, x, y, vprev, partials, stats, lz, jsq, st);
+        if (b->dm.ns == 4 && b->dm.n_chunks == 3)
+            return apply_impl<CPLX, AT, IDX_HASH, MODE, 35 + F>(b, x, y, vprev, partials, stats, lz, jsq, st);
+        if (MODE != 1) {
+            if (b->dm.ns == 2) return apply_impl<CPLX, AT, IDX_HASH, MODE, 16 + F>(b, x, y, vprev, partials, stats, lz, jsq, st);
+            if (b->dm.ns == 3) return apply_impl<CPLX, AT, IDX_HASH, MODE, 24 + F>(b, x, y, vprev, partials, stats, lz, jsq, st);
+            if (b->dm.ns == 4) return apply_impl<CPLX, AT, IDX_HASH, MODE, 32 + F>(b, x, y, vprev, partials, stats, lz, jsq, st);
+        }
+    }
     // four sublattices with one to three chunks: chunk count fixed too
     if (b->dm.ns == 4 && b->dm.n_chunks == 1)
         return apply_impl<CPLX, AT, IDX_HASH, MODE, 33>(b, x, y, vprev, partials, stats, lz, jsq, st);
