@@ -50,6 +50,7 @@ struct Ctx {
     const uint32_t *div_val;
     const BondLds *bonds;
     const uint16_t *rank;
+    const uint16_t *pos1;        // two-stage search: source block at position 1 | its state bit offset << 8
 };
 
 __device__ __forceinline__ void lds_copy(char *dst, const void *src, uint32_t bytes)
@@ -83,6 +84,7 @@ __device__ __forceinline__ Ctx<AT> stage(const DevModel &dm, char *lds)
     c.div_val = (const uint32_t *)(lds + dm.off_divval);
     c.bonds = (const BondLds *)(lds + dm.off_bonds);
     c.rank = (const uint16_t *)(lds + dm.off_rank);
+    c.pos1 = (const uint16_t *)(lds + dm.off_pos1);
     return c;
 }
 
@@ -241,15 +243,16 @@ __device__ __forceinline__ uint64_t find_rep_ns(const Ctx<AT> &c, uint64_t s, ui
 // The same search in two stages, for groups with many candidates per search.
 // Every candidate's top block is MinRep, so the image order is decided first
 // by the block landing at position 1.  Stage 1 images only that block for
-// every candidate of a Sym list (one table entry chunk per chunk instead of
-// all blocks) and keeps the candidates attaining its minimum in a bit mask;
-// stage 2 assembles the full image of those few.  The minimum and the
-// minimiser chosen (the first in list order) are those of find_rep_ns.
-// Lists longer than 64 candidates take the one-stage loop.
+// every candidate of a Sym list (the per-permutation table pos1 names its
+// source block and that block's bit offset in the state) and keeps the
+// candidates attaining its minimum in a bit mask; stage 2 assembles the full
+// image of those few.  The minimum and the minimiser chosen (the first in
+// list order) are those of find_rep_ns.  Lists longer than 32 candidates take
+// the one-stage loop.
 template <typename AT, int NS, int NC>
 __device__ __forceinline__ uint64_t find_rep_staged(const Ctx<AT> &c, uint64_t s, uint32_t &g_best)
 {
-    static_assert(NS >= 2 && NS <= 4, "two-stage search for 2 to 4 sublattices");
+    static_assert(NS >= 2, "a position-1 block needs two sublattices");
     const int N = c.N, m = c.m, cb = c.cb;
     const int nc = NC > 0 ? NC : c.nc;
     const uint32_t P = c.mmask + 1;
@@ -264,7 +267,6 @@ __device__ __forceinline__ uint64_t find_rep_staged(const Ctx<AT> &c, uint64_t s
 #pragma unroll
     for (int X = 0; X < NS; ++X) tie |= (uint32_t)((c.rep[X * P + sx[X]] & 0xFFFFu) == minr) << X;
     const uint64_t top = (uint64_t)minr << (N - m);
-    const uint32_t sh1 = (uint32_t)(N - 2 * m);   // shift of the block at position 1
     constexpr uint32_t kImgMask = ActTraits<AT>::kPos ? (1u << ActTraits<AT>::kPosShift) - 1u : 0xFFFFFFFFu;
     uint64_t best = ~0ull;
     uint32_t bg = 0;
@@ -293,7 +295,7 @@ __device__ __forceinline__ uint64_t find_rep_staged(const Ctx<AT> &c, uint64_t s
         const uint32_t sy = (uint32_t)(s >> (N - (Y + 1) * m)) & c.mmask;
         const uint32_t off = c.rep[Y * P + sy] >> 16;
         const uint32_t cnt = c.sym[off];
-        if (cnt > 64) {
+        if (cnt > 32) {
             for (uint32_t k = 1; k <= cnt; ++k) {
                 const uint32_t ent = c.sym[off + k];
                 const uint64_t v = full_image(ent);
@@ -305,50 +307,30 @@ __device__ __forceinline__ uint64_t find_rep_staged(const Ctx<AT> &c, uint64_t s
             continue;
         }
         // stage 1: the position-1 block of every candidate
-        uint32_t min1 = 0xFFFFFFFFu;
-        uint64_t keep = 0;
+        uint32_t min1 = 0xFFFFFFFFu, keep = 0;
         for (uint32_t k = 0; k < cnt; ++k) {
             const uint32_t ent = c.sym[off + 1 + k];
             const uint32_t u = (ent >> 16) & 0x7FFFu;
-            // the source block landing at position 1 (block shifts of u: one
-            // byte per source block; four of them form one aligned word)
-            uint32_t src = 0, sxs = sx[0];
-            if constexpr (NS == 4) {
-                const uint32_t shw = *(const uint32_t *)(c.shift + u * NS);
-#pragma unroll
-                for (int X = 1; X < NS; ++X)
-                    if (((shw >> (8 * X)) & 0xFFu) == sh1) {
-                        src = X;
-                        sxs = sx[X];
-                    }
-            } else {
-#pragma unroll
-                for (int X = 1; X < NS; ++X)
-                    if (c.shift[u * NS + X] == sh1) {
-                        src = X;
-                        sxs = sx[X];
-                    }
-            }
-            const AT *t = c.act + (((size_t)u * NS + src) * nc << cb);
+            const uint32_t pw = c.pos1[u];
+            const uint32_t sxs = (uint32_t)(s >> (pw >> 8)) & c.mmask;
+            const AT *t = c.act + (((u * (uint32_t)NS + (pw & 0xFFu)) * (uint32_t)nc) << cb);
             uint32_t blk = 0;
             if (NC > 0) {
 #pragma unroll
-                for (int k2 = 0; k2 < (NC > 0 ? NC : 1); ++k2) blk |= t[(k2 << cb) | ((sxs >> (k2 * cb)) & c.cmask)];
+                for (int k2 = 0; k2 < (NC > 0 ? NC : 1); ++k2)
+                    blk |= t[(k2 << cb) | __builtin_amdgcn_ubfe(sxs, k2 * cb, cb)];
             } else {
-                for (int k2 = 0; k2 < nc; ++k2) blk |= t[(k2 << cb) | ((sxs >> (k2 * cb)) & c.cmask)];
+                for (int k2 = 0; k2 < nc; ++k2) blk |= t[(k2 << cb) | __builtin_amdgcn_ubfe(sxs, k2 * cb, cb)];
             }
-            blk &= kImgMask;
-            if (ent >> 31) blk ^= c.mmask;
-            if (blk < min1) {
-                min1 = blk;
-                keep = 1ull << k;
-            } else if (blk == min1) {
-                keep |= 1ull << k;
-            }
+            blk = (blk & kImgMask) ^ ((ent >> 31) ? c.mmask : 0u);
+            const uint32_t bit = 1u << k;
+            const bool lt = blk < min1, eq = blk == min1;
+            keep = lt ? bit : (eq ? (keep | bit) : keep);
+            min1 = lt ? blk : min1;
         }
         // stage 2: full images of the survivors, in list order
         while (keep) {
-            const int k = __builtin_ctzll(keep);
+            const int k = __builtin_ctz(keep);
             keep &= keep - 1;
             const uint32_t ent = c.sym[off + 1 + k];
             const uint64_t v = full_image(ent);

@@ -79,7 +79,7 @@ struct DevModel {
     int act_bytes;             // 1, 2 or 4 bytes per action-table entry
     const char *blob;
     uint32_t off_rep, off_sym, off_act, off_shift, off_chi, off_div, off_divval, off_bonds, off_rank,
-        lds_total;
+        off_pos1, lds_total;
 };
 
 struct DevBasis {

@@ -703,6 +703,12 @@ static int upload_tables(ed_basis *b, hipStream_t st)
         bz[k].jhalf = 0.0;
         bz[k].jzhalf = 0.0;
     }
+    // two-stage search: for every permutation u, the source block landing at
+    // position 1 and that block's bit offset in the state
+    std::vector<uint16_t> pos1(b->staged ? t.nu : 0, 0);
+    for (int u = 0; u < (int)pos1.size(); ++u)
+        for (int X = 0; X < ns; ++X)
+            if (t.u_tgt[(size_t)u * ns + X] == 1) pos1[u] = (uint16_t)(X | (t.N - (X + 1) * m) << 8);
     // rank of every top-block value, staged only for the Limits index
     std::vector<uint16_t> rank(b->db.index_mode == IDX_LIMITS ? P : 1, 0);
     if (b->db.index_mode == IDX_LIMITS)
@@ -731,6 +737,7 @@ static int upload_tables(ed_basis *b, hipStream_t st)
         dm.off_divval = put(dvals.data(), dvals.size() * 4);
         dm.off_bonds = put(bz.data(), bz.size() * sizeof(BondLds));
         dm.off_rank = put(rank.data(), rank.size() * 2);
+        dm.off_pos1 = put(pos1.data(), pos1.size() * 2);
         // chunked action table [nu][ns][nc][2^cb]; wide entries of chunk 0
         // also carry the target block index
         const size_t ent = (size_t)t.nu * ns * nc << cb;

@@ -21,13 +21,15 @@ import numpy as np
 from . import _lib as L
 
 LDS_BUDGET = 160 * 1024 - 8192
+TWO_STAGE_MIN_CANDIDATES = 3.0   # the library's automatic search choice
 
 
 def _divisors(n):
     return [d for d in range(1, n + 1) if n % d == 0]
 
 
-def table_layout(n_sub, sub_bits, n_perms, sym_entries, n_elems, n_bonds, complex_chi=False, budget=LDS_BUDGET):
+def table_layout(n_sub, sub_bits, n_perms, sym_entries, n_elems, n_bonds, complex_chi=False, budget=LDS_BUDGET,
+                 two_stage=False):
     """Fewest action-table chunks whose LDS image fits the budget, as the
     library lays it out.  Returns (chunks, lds_bytes) or None.
 
@@ -38,6 +40,8 @@ def table_layout(n_sub, sub_bits, n_perms, sym_entries, n_elems, n_bonds, comple
       * the characters (8 B real or 16 B complex per element);
       * square roots of the stabiliser sizes and their inverses, and the divisors;
       * the bonds (24 B each);
+      * for the two-stage search, 2 B per permutation (the source block at
+        position 1 and its bit offset);
       * the chunked action table, with 2-byte entries for blocks of up to 12 sites and
         4-byte entries above.
     """
@@ -46,7 +50,7 @@ def table_layout(n_sub, sub_bits, n_perms, sym_entries, n_elems, n_bonds, comple
     n_div = len(_divisors(n_elems))
     fixed = (pad(4 * n_sub * P) + pad(4 * (n_sub * P + sym_entries)) + pad(n_perms * n_sub)
              + pad((16 if complex_chi else 8) * n_elems) + pad(16 * n_div) + pad(4 * n_div)
-             + pad(24 * max(n_bonds, 1)) + pad(2))
+             + pad(24 * max(n_bonds, 1)) + pad(2) + (pad(2 * n_perms) if two_stage else 0))
     esz = 2 if sub_bits <= 12 else 4
     for nc in range(1, sub_bits + 1):
         cb = math.ceil(sub_bits / nc)
@@ -85,10 +89,12 @@ def rank_decompositions(make_cluster, decompositions, n_up, samples=4000, seed=7
             continue
         try:
             info = L.ed_tables_info(h)
-            lay = table_layout(n_sub, info["sub_bits"], info["n_perms"], info["sym_entries"], info["n_elems"],
-                               cl.n_bonds)
             cfg = _random_configs(cl.n_sites, n_up, samples, seed)
             _, _, cand = L.ed_tables_find_rep(h, cfg)
+            # the library's automatic choice of the two-stage search
+            two_stage = 2 <= n_sub <= 4 and float(cand.mean()) >= TWO_STAGE_MIN_CANDIDATES
+            lay = table_layout(n_sub, info["sub_bits"], info["n_perms"], info["sym_entries"], info["n_elems"],
+                               cl.n_bonds, two_stage=two_stage)
         finally:
             L.ed_tables_free(h)
         rec = dict(n_sub=n_sub, superlattice=M, sub_bits=info["sub_bits"], fits=lay is not None,
