@@ -48,7 +48,7 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_05028_amd", "csrc", f)
 MEASURED_TRAFFIC = {
     # (workload, n_sublat, index, chunk_bits): (kernel sha256, fetch bytes, write bytes)
     ("square40_j1j2", 4, "hash-slot", 5): (
-        "8ecaa2d7040cc556090a1606ce9a3776aa5e63ab73cb9ca0a63509af3b044522", 4.93058e12, 3.4473e9),
+        "de906a54c34fb18bd415f111e25fd8c1e108ae9cf51712905980dca4cacb3336", 4.93163e+12, 3.44728e+09),
 }
 
 
