@@ -103,8 +103,9 @@ __device__ __forceinline__ uint64_t place_block(const Ctx<AT> &c, uint32_t u, in
 {
     if (ActTraits<AT>::kPos) {
         const uint32_t img = e & ((1u << ActTraits<AT>::kPosShift) - 1u);
-        const int pos = (int)(e >> ActTraits<AT>::kPosShift);
-        return (uint64_t)img << (c.N - (pos + 1) * c.m);
+        const uint32_t pos = e >> ActTraits<AT>::kPosShift;
+        // position and block width are below 2^24: full-rate 24-bit multiply
+        return (uint64_t)img << ((uint32_t)(c.N - c.m) - __umul24(pos, (uint32_t)c.m));
     }
     return (uint64_t)e << c.shift[u * ns + X];
 }
@@ -214,7 +215,7 @@ __device__ __forceinline__ uint64_t find_rep_ns(const Ctx<AT> &c, uint64_t s, ui
         for (uint32_t k = 1; k <= cnt; ++k) {
             const uint32_t ent = c.sym[off + k];
             const uint32_t u = (ent >> 16) & 0x7FFFu;
-            const AT *tu = c.act + ((size_t)u * NS * nc << cb);
+            const AT *tu = c.act + ((u * (uint32_t)(NS * nc)) << cb);
             uint64_t v = 0;
 #pragma unroll
             for (int X = 0; X < NS; ++X) {
@@ -273,7 +274,7 @@ __device__ __forceinline__ uint64_t find_rep_staged(const Ctx<AT> &c, uint64_t s
     // full image of candidate entry ent
     auto full_image = [&](uint32_t ent) -> uint64_t {
         const uint32_t u = (ent >> 16) & 0x7FFFu;
-        const AT *tu = c.act + ((size_t)u * NS * nc << cb);
+        const AT *tu = c.act + ((u * (uint32_t)(NS * nc)) << cb);
         uint64_t v = 0;
 #pragma unroll
         for (int X = 0; X < NS; ++X) {
