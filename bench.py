@@ -115,6 +115,29 @@ def bench_allk(args):
     reps = max(args.hv_reps, 1)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
+    if args.profile_only:
+        # the first group only: build, one untimed and --hv-reps timed batched
+        # launches, then one plain copy of the vector (byte-counter calibration)
+        mb = ed.MultiBasis.from_workloads(ws[:args.batch])
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(0)
+        x = torch.randn((mb.dim, mb.K), dtype=torch.complex128, device="cuda", generator=gen)
+        y = mb.empty()
+        mb.apply(J, x, out=y)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            mb.apply(J, x, out=y)
+        ev1.record()
+        torch.cuda.synchronize()
+        _, sh = mb.stats()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"hv_ms": ev0.elapsed_time(ev1) / reps, "K": mb.K, "shared_terms": int(sh),
+                          "lanes_per_row": mb.info()["lanes_per_row"], "copy_bytes_each_way": x.numel() * 16}))
+        mb.close()
+        return
+
     # one launch per sector, sector by sector (each with its own basis and index)
     per_ms, per_terms = 0.0, 0
     for w in ws:
@@ -242,7 +265,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="build, then run --hv-reps H.v launches only")
-    ap.add_argument("--batch", type=int, default=12, help="sectors per batched launch (triangular36_allk)")
+    ap.add_argument("--batch", type=int, default=16, help="sectors per batched launch (triangular36_allk)")
     ap.add_argument("--sectors", default="all", choices=["all", "inequivalent"],
                     help="triangular36_allk: all 36 momenta, or the 20 inequivalent ones")
     ap.add_argument("--adjoint", action="store_true",

@@ -109,6 +109,9 @@ typedef struct {
                                first and assemble only the candidates minimising it (2 to 4
                                sublattices, else ED_ERR_UNSUPPORTED); 0 = two-stage when a host
                                sample of the search averages at least 3 candidates               */
+    int32_t lanes_per_row;  /* batched H.v (ed_build_multi): 1, 2 or 4 lanes share a row, each
+                               running the row's searches and holding ceil(K / lanes) of its
+                               sectors; 0 = 1 lane for K <= 2, 2 lanes for K <= 8, else 4         */
 } ed_tuning_t;
 
 #define ED_SEARCH_ONE_STAGE 1
@@ -292,6 +295,7 @@ typedef struct {
     int64_t n_slots;
     int64_t device_bytes;
     double build_ms;
+    int32_t lanes_per_row;      /* lanes per row of the batched H.v kernel     */
 } ed_multi_info_t;
 
 #define ED_LANCZOS_NO_GRAPH 1   /* ed_lanczos_batched: launch the step kernels directly */

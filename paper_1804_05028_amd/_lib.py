@@ -46,7 +46,8 @@ class ed_tuning_t(ctypes.Structure):
     _fields_ = [("limits_bits", ctypes.c_int32), ("index_mode", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("chunk_bits", ctypes.c_int32), ("hash_load_pct", ctypes.c_int32),
-                ("table_entry_bytes", ctypes.c_int32), ("search_mode", ctypes.c_int32)]
+                ("table_entry_bytes", ctypes.c_int32), ("search_mode", ctypes.c_int32),
+                ("lanes_per_row", ctypes.c_int32)]
 
 
 ED_SEARCH_ONE_STAGE = 1
@@ -76,7 +77,8 @@ class ed_multi_info_t(ctypes.Structure):
                 ("n_up", ctypes.c_int32), ("n_sublat", ctypes.c_int32), ("n_elems", ctypes.c_int32),
                 ("n_bonds", ctypes.c_int32), ("chunk_bits", ctypes.c_int32),
                 ("table_entry_bytes", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
-                ("n_slots", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double)]
+                ("n_slots", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
+                ("lanes_per_row", ctypes.c_int32)]
 
 
 ED_LANCZOS_NO_GRAPH = 1
@@ -245,7 +247,8 @@ def _tuning(tuning):
     return ed_tuning_t(int(tuning.get("limits_bits", 0)), int(tuning.get("index_mode", 0)),
                        int(tuning.get("block_threads", 0)), int(tuning.get("blocks_per_cu", 0)),
                        int(tuning.get("chunk_bits", 0)), int(tuning.get("hash_load_pct", 0)),
-                       int(tuning.get("table_entry_bytes", 0)), int(tuning.get("search_mode", 0)))
+                       int(tuning.get("table_entry_bytes", 0)), int(tuning.get("search_mode", 0)),
+                       int(tuning.get("lanes_per_row", 0)))
 
 
 def ed_build_basis(arrays: ModelArrays, n_up, tuning=None, stream=None):

@@ -168,7 +168,9 @@ static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, co
         b->tuning.chunk_bits > 16 || b->tuning.hash_load_pct < 0 || b->tuning.hash_load_pct > 90 ||
         (b->tuning.table_entry_bytes != 0 && b->tuning.table_entry_bytes != 1 && b->tuning.table_entry_bytes != 2 &&
          b->tuning.table_entry_bytes != 4) ||
-        b->tuning.search_mode < 0 || b->tuning.search_mode > ED_SEARCH_TWO_STAGE) {
+        b->tuning.search_mode < 0 || b->tuning.search_mode > ED_SEARCH_TWO_STAGE ||
+        (b->tuning.lanes_per_row != 0 && b->tuning.lanes_per_row != 1 && b->tuning.lanes_per_row != 2 &&
+         b->tuning.lanes_per_row != 4)) {
         delete b;
         return set_error(ED_ERR_ARG, "tuning fields out of range");
     }
@@ -454,6 +456,7 @@ int ed_multi_info(const ed_multi_t *mb, ed_multi_info_t *info)
     info->n_slots = b->n_slots;
     info->device_bytes = b->device_bytes;
     info->build_ms = mb->build_ms;
+    info->lanes_per_row = ed::multi_lanes_per_row(mb);
     return ED_OK;
 }
 

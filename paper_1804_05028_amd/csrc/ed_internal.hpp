@@ -161,6 +161,7 @@ struct ed_multi {
 namespace ed {
 // Kernel launchers (ed_kernels.hip)
 int launch_basis_build(ed_basis *b, void *stream);
+int multi_lanes_per_row(const ed_multi *mb);
 int launch_apply(const ed_basis *b, const double *J, const double *Jz, const void *x, void *y, void *stream, int stats_mode,
                  unsigned long long *stats_dev);
 int launch_backward_J(const ed_basis *b, const double *J, const void *x, const void *gy, double *gJ_host,

@@ -100,18 +100,34 @@ __global__ void k_multi_pack_index(const uint32_t *slot_of, const uint64_t *mask
         *(uint64_t *)(slots + (size_t)slot_of[j] * 16 + 8) = (uint64_t)j | (masks[j] << 32);
 }
 
+// (ar, ai) += amp * chi * xv with the fused multiply-adds written out, so
+// that every kernel instance rounds the same way whatever the compiler would
+// contract on its own
+__device__ __forceinline__ void cmac(double &ar, double &ai, double amp, double2 chi, double2 xv)
+{
+    ar = fma(amp, fma(chi.x, xv.x, -(chi.y * xv.y)), ar);
+    ai = fma(amp, fma(chi.x, xv.y, chi.y * xv.x), ai);
+}
+
 // ---------------------------------------------------------------------------
-// Batched H.v.  KB is the compile-time bound of the sector loop (K <= KB).
+// Batched H.v.  KB is the compile-time bound of the sector loop.  SPLIT lanes
+// share a row: each runs the row's searches and probes (same addresses, so
+// the requests of a load instruction merge) and owns ceil(K / SPLIT) of its
+// sectors, which divides the per-lane accumulator and amplitude registers by
+// SPLIT and raises the number of waves a compute unit holds.
 // MODE 0: y = H x, or w = H v - beta_prev[k] vprev when vprev is given
 // (Lanczos; y may be vprev itself: each element is read and then written by
-// the same thread).  MODE 1: per-sector term counts (D_k + kept_k) in stats[0..K),
-// shared kept terms in stats[K], dropped lookups in stats[K+1].
+// the same thread).  MODE 1 (SPLIT 1): per-sector term counts (D_k + kept_k)
+// in stats[0..K), shared kept terms in stats[K], dropped lookups in
+// stats[K+1].
 // ---------------------------------------------------------------------------
-template <typename AT, int NS, int KB, int MODE>
+template <typename AT, int NS, int KB, int MODE, int SPLIT>
 __global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
     k_apply_multi(DevModel dm, DevBasis db, MultiDev md, const double2 *__restrict__ x, double2 *y,
                   const double2 *vprev, const MlzSector *__restrict__ sec, double *stats, double jsq)
 {
+    static_assert(MODE == 0 || SPLIT == 1, "term counting runs one lane per row");
+    static_assert(kWave % SPLIT == 0, "lanes per row must divide the wave");
     extern __shared__ __align__(16) char lds[];
     const Ctx<AT> c = stage<AT>(dm, lds);
     double2 *chik = (double2 *)(lds + md.chi_off);
@@ -122,18 +138,25 @@ __global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
     const int64_t D = db.dim;
     const uint64_t smask = (1ull << db.slot_log2) - 1ull;
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // this lane's row within the wave's group of rows, and its sectors
+    constexpr int kRows = kWave / SPLIT;
+    const int rl = lane / SPLIT;
+    const int KH = (K + SPLIT - 1) / SPLIT;
+    const int koff = (lane % SPLIT) * KH;
+    const int KL = max(min(K - koff, KH), 0);   // sectors of this lane: koff .. koff + KL - 1
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t n_waves = (int64_t)gridDim.x * blockDim.x / kWave;
     double shared = 0.0, dropped = 0.0;
     double ar[KB], ai[KB];
     if (MODE == 1) {
 #pragma unroll
         for (int k = 0; k < KB; ++k) ar[k] = 0.0;
     }
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < D; i0 += stride) {
-        const int64_t i = i0 + lane;
+    for (int64_t i0 = wave * kRows; i0 < D; i0 += n_waves * kRows) {
+        const int64_t i = i0 + rl;
         const bool row_ok = i < D;
         const uint64_t e = row_ok ? db.states[i] : 0ull;
-        const uint64_t mi = row_ok ? md.masks[i] : 0ull;
+        const uint64_t mi = row_ok ? md.masks[i] >> koff : 0ull;   // bit k: sector koff + k
         const uint64_t s = e & kStateMask;
         const double rs_i = c.div_rsqrt[e >> kNormShift];
         if (MODE == 0) {
@@ -178,16 +201,18 @@ __global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
                 q = load_slot<false>(db.slots, sl);
             }
             const bool found = q.x != kEmpty;
-            const uint64_t mij = found ? (mi & (q.y >> 32)) : 0ull;
+            const uint64_t mij = found ? (mi & (q.y >> (32 + koff))) : 0ull;
             // the target's amplitudes are requested before the next term's
             // search, which hides their latency
-            constexpr bool kPre = KB <= 16;   // registers allow holding the next row's amplitudes
+            // registers allow holding the next row's amplitudes (split rows
+            // trade the prefetch for more resident waves, except for 4 sectors)
+            constexpr bool kPre = KB <= 16 && (SPLIT == 1 || KB <= 4);
             double2 xv[kPre ? KB : 1];
             if (MODE == 0 && kPre) {
-                const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K;
+                const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K + koff;
 #pragma unroll
                 for (int k = 0; k < KB; ++k)
-                    xv[k] = (k < K && ((mij >> k) & 1ull)) ? xj[k] : make_double2(0.0, 0.0);
+                    xv[k] = (k < KL && ((mij >> k) & 1ull)) ? xj[k] : make_double2(0.0, 0.0);
             }
             if (term + 1 < n_terms) {
                 const BondLds bd = c.bonds[pop_bond(am)];
@@ -208,44 +233,35 @@ __global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
                 continue;
             }
             const double amp = jh * rs_i * c.div_sqrt[q.x >> kNormShift];
-            const double2 *ch = chik + (size_t)g * K;
+            const double2 *ch = chik + (size_t)g * K + koff;
             if (kPre) {
 #pragma unroll
                 for (int k = 0; k < (kPre ? KB : 1); ++k) {
-                    if (k < K) {
-                        const double2 cv = ch[k];
-                        ar[k] += amp * (cv.x * xv[k].x - cv.y * xv[k].y);
-                        ai[k] += amp * (cv.x * xv[k].y + cv.y * xv[k].x);
-                    }
+                    if (k < KL) cmac(ar[k], ai[k], amp, ch[k], xv[k]);
                 }
             } else {
-                const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K;
+                const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K + koff;
 #pragma unroll
                 for (int k = 0; k < KB; ++k) {
-                    if (k < K && ((mij >> k) & 1ull)) {
-                        const double2 xw = xj[k];
-                        const double2 cv = ch[k];
-                        ar[k] += amp * (cv.x * xw.x - cv.y * xw.y);
-                        ai[k] += amp * (cv.x * xw.y + cv.y * xw.x);
-                    }
+                    if (k < KL && ((mij >> k) & 1ull)) cmac(ar[k], ai[k], amp, ch[k], xj[k]);
                 }
             }
         }
         if (MODE == 1 || !row_ok) continue;
         const double d = jsq - anti_sum;
-        double2 *yi = y + (size_t)i * K;
-        const double2 *xi = x + (size_t)i * K;
+        double2 *yi = y + (size_t)i * K + koff;
+        const double2 *xi = x + (size_t)i * K + koff;
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
-            if (k < K) {
+            if (k < KL) {
                 double2 out = make_double2(0.0, 0.0);
                 if ((mi >> k) & 1ull) {
                     const double2 xv = xi[k];
                     out.x = d * xv.x + ar[k];
                     out.y = d * xv.y + ai[k];
                     if (vprev) {
-                        const double bp = sec[k].beta_prev;
-                        const double2 vp = vprev[(size_t)i * K + k];
+                        const double bp = sec[koff + k].beta_prev;
+                        const double2 vp = vprev[(size_t)i * K + koff + k];
                         out.x -= bp * vp.x;
                         out.y -= bp * vp.y;
                     }
@@ -446,12 +462,12 @@ __global__ void __launch_bounds__(kMlzThreads) k_mlz_normalize(double2 *w, int64
 // ---------------------------------------------------------------------------
 static int table_width(const ed_basis *b) { return b->dm.act_bytes; }
 
-template <int MODE, typename AT, int NS, int KB>
+template <int MODE, typename AT, int NS, int KB, int SPLIT>
 static int multi_launch_impl(const ed_multi *mb, const void *x, void *y, const void *vprev, const void *sec,
                              double *stats, double jsq, hipStream_t st)
 {
     const ed_basis *b = mb->base;
-    auto kern = k_apply_multi<AT, NS, KB, MODE>;
+    auto kern = k_apply_multi<AT, NS, KB, MODE, SPLIT>;
     const int bound = KB > 8 ? 512 : 1024;
     int threads = b->tuning.block_threads > 0 ? std::min(b->tuning.block_threads, bound) : bound;
     MultiDev md;
@@ -465,7 +481,7 @@ static int multi_launch_impl(const ed_multi *mb, const void *x, void *y, const v
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
     if (b->tuning.blocks_per_cu > 0) per_cu = std::min(per_cu, b->tuning.blocks_per_cu);
-    const int64_t need = (b->db.dim + threads - 1) / threads;
+    const int64_t need = (b->db.dim * SPLIT + threads - 1) / threads;
     int64_t grid = std::min<int64_t>((int64_t)per_cu * num_cus(), need);
     grid = std::max<int64_t>(grid, 1);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, st, b->dm, b->db, md, (const double2 *)x,
@@ -475,14 +491,39 @@ static int multi_launch_impl(const ed_multi *mb, const void *x, void *y, const v
     return ED_OK;
 }
 
+// lanes per row of the batched H.v: the caller's choice, else 1 lane for up
+// to 2 sectors, 2 lanes for up to 8 and 4 lanes above (measured on the
+// 36-site triangular momentum sectors: each lane then holds at most 4
+// sectors for K <= 16 and prefetches their next amplitudes)
+int multi_lanes_per_row(const ed_multi *mb)
+{
+    const int t = mb->base->tuning.lanes_per_row;
+    if (t > 0) return t;
+    return mb->K <= 2 ? 1 : (mb->K <= 8 ? 2 : 4);
+}
+
 template <int MODE, typename AT, int NS>
 static int multi_launch_kb(const ed_multi *mb, const void *x, void *y, const void *vprev, const void *sec,
                            double *stats, double jsq, hipStream_t st)
 {
-    if (mb->K <= 4) return multi_launch_impl<MODE, AT, NS, 4>(mb, x, y, vprev, sec, stats, jsq, st);
-    if (mb->K <= 8) return multi_launch_impl<MODE, AT, NS, 8>(mb, x, y, vprev, sec, stats, jsq, st);
-    if (mb->K <= 16) return multi_launch_impl<MODE, AT, NS, 16>(mb, x, y, vprev, sec, stats, jsq, st);
-    return multi_launch_impl<MODE, AT, NS, 32>(mb, x, y, vprev, sec, stats, jsq, st);
+    const int K = mb->K;
+    const int split = MODE == 0 ? multi_lanes_per_row(mb) : 1;
+    const int kh = (K + split - 1) / split;   // sectors per lane
+#define ED_KB(KB, S) return multi_launch_impl<MODE, AT, NS, KB, (MODE == 0 ? S : 1)>(mb, x, y, vprev, sec, stats, jsq, st)
+    if (MODE == 0 && split == 2) {
+        if (kh <= 4) ED_KB(4, 2);
+        if (kh <= 8) ED_KB(8, 2);
+        ED_KB(16, 2);
+    }
+    if (MODE == 0 && split == 4) {
+        if (kh <= 4) ED_KB(4, 4);
+        ED_KB(8, 4);
+    }
+    if (kh <= 4) ED_KB(4, 1);
+    if (kh <= 8) ED_KB(8, 1);
+    if (kh <= 16) ED_KB(16, 1);
+    ED_KB(32, 1);
+#undef ED_KB
 }
 
 template <int MODE>

@@ -1,0 +1,82 @@
+"""Batched H.v with 1, 2 and 4 lanes per row.
+
+Every lane of a row runs the same searches and accumulates its own sectors
+in the same term order, so the result must not depend on the number of lanes
+per row, bit for bit; the one-lane result is checked against the oracle of
+each sector.  K = 5 leaves one lane of four without sectors; K = 12 gives two
+lanes 6 sectors each and four lanes 3 each.
+"""
+import numpy as np
+import pytest
+import torch
+
+from ed_inputs import lattice as lat
+from ed_inputs import vectors as vec
+from ed_inputs import workloads as wl
+from oracle import bruteforce as bf
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+def _ed():
+    from paper_1804_05028_amd import ed
+    return ed
+
+
+def _sectors(K):
+    c = wl.square_4x4().cluster
+    return [wl.Workload(f"sq16_k{k}", c, lat.characters(c, k), 8, np.ones(c.n_bonds)) for k in range(K)]
+
+
+def _x(dim, K, seed):
+    re = vec.normal_vector(dim * K, seed=seed, normalise=False)
+    im = vec.normal_vector(dim * K, seed=seed + 1000, normalise=False)
+    return (re + 1j * im).reshape(dim, K)
+
+
+@pytest.mark.parametrize("K", [5, 12, 16])
+def test_lanes_per_row_bit_identical(K):
+    ed = _ed()
+    ws = _sectors(K)
+    ys, alphas, betas, x, masks = {}, {}, {}, None, None
+    for lanes in (1, 2, 4):
+        print(f"[lanes] K={K} lanes={lanes}", flush=True)
+        mb = ed.MultiBasis.from_workloads(ws, {"lanes_per_row": lanes})
+        try:
+            assert mb.info()["lanes_per_row"] == lanes
+            if x is None:
+                x = _x(mb.dim, mb.K, 31)
+                masks = mb.masks()
+            ys[lanes] = mb.apply(ws[0].J, torch.as_tensor(x).cuda()).cpu().numpy()
+            res = mb.lanczos(ws[0].J, torch.as_tensor(x).cuda(), 20)
+            alphas[lanes], betas[lanes] = res["alpha"], res["beta"]
+        finally:
+            mb.close()
+    for lanes in (2, 4):
+        assert np.array_equal(ys[lanes], ys[1]), lanes
+        assert np.array_equal(alphas[lanes], alphas[1]), lanes
+        assert np.array_equal(betas[lanes], betas[1]), lanes
+    for k, w in enumerate(ws):
+        sel = ((masks >> np.uint64(k)) & np.uint64(1)).astype(bool)
+        m = bf.Model.from_workload(w)
+        st, stab = bf.basis(m, w.n_up)
+        ref, _, _ = bf.apply(m, st, stab, x[sel, k])
+        assert np.linalg.norm(ys[1][sel, k] - ref) <= RTOL * np.linalg.norm(ref), k
+        assert np.all(ys[1][~sel, k] == 0)
+
+
+def test_automatic_lanes_per_row():
+    ed = _ed()
+    c = lat.triangular((2, 2), (-2, 4), rotations=False, mirrors=False, spin_flip=True, superlattice=wl.TRI_3,
+                       name="triangular12Tf")
+    tri24 = [wl.Workload("tri12", c, lat.characters(c, k, flip_parity=f), 6, np.ones(c.n_bonds))
+             for k in range(12) for f in (1, -1)]
+    for ws, want in ((_sectors(2), 1), (_sectors(3), 2), (_sectors(8), 2), (_sectors(9), 4), (_sectors(16), 4),
+                     (tri24, 4)):
+        mb = ed.MultiBasis.from_workloads(ws)
+        try:
+            assert mb.info()["lanes_per_row"] == want, len(ws)
+        finally:
+            mb.close()

@@ -263,10 +263,11 @@ def test_host_find_rep_at_the_56_site_limit():
         L.ed_tables_free(h)
 
 
-def test_search_mode_is_validated_before_any_device_work():
+def test_tuning_modes_are_validated_before_any_device_work():
     # both checks run on the host tables, before the first HIP call
     w = wl.square_20_j1j2(n_sub=5)
     arrays = _arrays(w.cluster, w.chi)
     _expect("ED_ERR_UNSUPPORTED", lambda: L.ed_build_basis(arrays, w.n_up, {"search_mode": L.ED_SEARCH_TWO_STAGE}))
     _expect("ED_ERR_ARG", lambda: L.ed_build_basis(arrays, w.n_up, {"search_mode": 3}))
     _expect("ED_ERR_ARG", lambda: L.ed_build_basis(arrays, w.n_up, {"search_mode": -1}))
+    _expect("ED_ERR_ARG", lambda: L.ed_build_basis(arrays, w.n_up, {"lanes_per_row": 3}))
