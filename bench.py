@@ -161,13 +161,20 @@ def bench_allk(args):
         b.close()
         torch.cuda.empty_cache()
 
-    # batched: sectors in groups of --batch, search and lookup shared per group
-    groups = [ws[i:i + args.batch] for i in range(0, len(ws), args.batch)]
+    # batched: sectors in groups of --batch (or the autotuned schedule), search
+    # and lookup shared per group
+    tuned = None
+    if args.autotune:
+        from paper_1804_05028_amd import autotune as at
+        tuned = at.autotune_batched(ws, log=lambda m: print(m, file=sys.stderr, flush=True))
+        groups = [(ws[i:i + k], lanes) for i, k, lanes in tuned["groups"]]
+    else:
+        groups = [(ws[i:i + args.batch], 0) for i in range(0, len(ws), args.batch)]
     hv_ms, terms, shared_terms, lz_s, lz_steps, build_s, e0 = 0.0, 0, 0, 0.0, 0, 0.0, []
     info = None
-    for grp in groups:
+    for grp, lanes in groups:
         t0 = time.perf_counter()
-        mb = ed.MultiBasis.from_workloads(grp)
+        mb = ed.MultiBasis.from_workloads(grp, {"lanes_per_row": lanes} if lanes else None)
         torch.cuda.synchronize()
         build_s += time.perf_counter() - t0
         info = mb.info()
@@ -213,7 +220,8 @@ def bench_allk(args):
         "vs_baseline": None,
         "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": "triangular36_allk", "n_sectors": len(ws), "batch": args.batch,
+        "config": {"workload": "triangular36_allk", "n_sectors": len(ws),
+                   "batch": tuned["batch"] if tuned else args.batch,
                    "description": f"Heisenberg triangular 36 (6,0)x(0,6), 36 T, {len(ws)} momentum sectors "
                                   f"({args.sectors}), Sz=0",
                    "shared_rows": info["dim"] if info else 0, "n_sublat": info["n_sublat"] if info else 0,
@@ -229,6 +237,8 @@ def bench_allk(args):
         "basis_build_s": build_s,
         "lowest_e0": min(e0) if e0 else None,
     }
+    if tuned is not None:
+        out["autotune"] = {"groups": tuned["groups"], "est_ms": tuned["est_ms"], "trials": len(tuned["trials"])}
     print(json.dumps(out))
 
 

@@ -6,7 +6,8 @@ per compute unit, one- or two-stage representative search), build the basis, tim
 on the current stream, and keep the fastest.  Configurations the library
 rejects (tables that do not fit in LDS, unsupported entry widths) are
 recorded and skipped.  Every candidate computes the same H.v; only its speed
-differs.
+differs.  For batched sectors, autotune_batched picks the group size and
+the lanes per row of each group.
 """
 from __future__ import annotations
 
@@ -108,6 +109,59 @@ def autotune_decompositions(make_workload_for, decompositions, n_up, top=3, **kw
     return best, results, ranked
 
 
+def _time_batched(mb, J, reps):
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    x = torch.randn((mb.dim, mb.K), dtype=torch.complex128, device="cuda", generator=gen)
+    y = mb.empty()
+    mb.apply(J, x, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        mb.apply(J, x, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def autotune_batched(workloads, batches=(4, 8, 12, 16), lanes=(1, 2, 4), reps=1, log=None):
+    """Schedule of batched launches for the sectors `workloads` (one group,
+    shared cluster, n_up and couplings).
+
+    The sectors run in consecutive groups of B (the last group holds the
+    remainder).  For every B in `batches` and every group size that schedule
+    needs, each lanes-per-row value is timed on the first sectors of that
+    size; the schedule with the smallest summed time wins.  Returns
+    {"batch", "groups": [(first, size, lanes_per_row)], "est_ms", "trials"}.
+    """
+    n = len(workloads)
+    J = workloads[0].J
+    best_of = {}   # group size -> (ms, lanes)
+    trials = []
+    sizes = sorted({min(b, n) for b in batches} | {n % b for b in batches if n % b and b < n})
+    for K in sizes:
+        for L in lanes:
+            mb = ed.MultiBasis.from_workloads(workloads[:K], {"lanes_per_row": L})
+            try:
+                ms = _time_batched(mb, J, reps)
+            finally:
+                mb.close()
+                torch.cuda.empty_cache()
+            trials.append({"K": K, "lanes_per_row": L, "hv_ms": ms})
+            if log:
+                log(f"[autotune] K={K} lanes_per_row={L}: {ms:.1f} ms")
+            if K not in best_of or ms < best_of[K][0]:
+                best_of[K] = (ms, L)
+    plans = []
+    for b in batches:
+        b = min(b, n)
+        groups = [(i, min(b, n - i)) for i in range(0, n, b)]
+        plans.append((sum(best_of[k][0] for _, k in groups), b, groups))
+    est, b, groups = min(plans)
+    return {"batch": b, "groups": [(i, k, best_of[k][1]) for i, k in groups], "est_ms": est, "trials": trials}
+
+
 def speedup_table(results):
     """(n_sub, tuning, ms, ms / best ms) rows, fastest first."""
     timed = sorted((r for r in results if "hv_ms" in r), key=lambda r: r["hv_ms"])
@@ -115,4 +169,4 @@ def speedup_table(results):
     return [(r["n_sub"], r["tuning"], r["hv_ms"], r["hv_ms"] / b) for r in timed]
 
 
-__all__ = ["autotune", "autotune_decompositions", "default_candidates", "speedup_table"]
+__all__ = ["autotune", "autotune_batched", "autotune_decompositions", "default_candidates", "speedup_table"]

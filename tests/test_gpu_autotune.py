@@ -59,3 +59,35 @@ def test_autotune_over_enumerated_decompositions():
         assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
     finally:
         b.close()
+
+
+def test_autotune_batched_schedule_covers_every_sector():
+    """The batched schedule tiles the sectors in order, picks a timed lane count
+    for each group, and its launches reproduce the oracle of every sector."""
+    from paper_1804_05028_amd import autotune as at
+    from paper_1804_05028_amd import ed
+    from ed_inputs import lattice as lat
+    c = wl.square_4x4().cluster
+    ws = [wl.Workload(f"sq16_k{k}", c, lat.characters(c, k), 8, np.ones(c.n_bonds)) for k in range(16)]
+    tuned = at.autotune_batched(ws, batches=(4, 6, 16), reps=2)
+    groups = tuned["groups"]
+    assert [g[0] for g in groups] == list(range(0, 16, tuned["batch"]))
+    assert sum(g[1] for g in groups) == 16 and all(g[2] in (1, 2, 4) for g in groups)
+    # sizes timed: 4, 6, 16 and the remainder 4 of batch 6
+    assert {t["K"] for t in tuned["trials"]} == {4, 6, 16}
+    for first, k, lanes in groups:
+        mb = ed.MultiBasis.from_workloads(ws[first:first + k], {"lanes_per_row": lanes})
+        try:
+            re = vec.normal_vector(mb.dim * k, seed=5, normalise=False)
+            x = (re + 0.5j * re[::-1]).reshape(mb.dim, k)
+            y = mb.apply(ws[0].J, torch.as_tensor(x).cuda()).cpu().numpy()
+            masks = mb.masks()
+            for j in range(k):
+                w = ws[first + j]
+                sel = ((masks >> np.uint64(j)) & np.uint64(1)).astype(bool)
+                m = bf.Model.from_workload(w)
+                st, stab = bf.basis(m, w.n_up)
+                ref, _, _ = bf.apply(m, st, stab, x[sel, j])
+                assert np.linalg.norm(y[sel, j] - ref) <= 1e-12 * np.linalg.norm(ref)
+        finally:
+            mb.close()
