@@ -106,11 +106,32 @@ def _allk_workloads(n_sub, which="all"):
     return [wl.triangular_36_momentum(k, n_sub=n_sub or 4) for k in ks]
 
 
+def _gamma_workloads(n_sub):
+    """The eight one-dimensional irreps at Gamma of the 36-site triangular
+    cluster's full group 36 T x C6v x spin flip: A1, A2, B1, B2 of C6v, each
+    with even and odd spin-flip parity."""
+    from ed_inputs import lattice as lat
+    from ed_inputs import workloads as wl
+    w0 = wl.triangular_36(n_sub=n_sub or 4)
+    c = w0.cluster
+    return [wl.Workload(f"triangular36_G{p}{'e' if f > 0 else 'o'}", c, lat.characters(c, 0, pc, f), w0.n_up, w0.J)
+            for p, pc in enumerate(lat.point_group_chars_1d(c.point_group)) for f in (1, -1)]
+
+
+BATCHED_WORKLOADS = {
+    "triangular36_allk": "36 T, {n} momentum sectors ({which})",
+    "triangular36_gamma": "36 T x C6v x flip, the {n} one-dimensional irreps at Gamma",
+}
+
+
 def bench_allk(args):
     """Batched all-sector H.v and Lanczos against one launch per sector."""
     import torch
     from paper_1804_05028_amd import ed
-    ws = _allk_workloads(args.n_sub, args.sectors)
+    if args.workload == "triangular36_gamma":
+        ws = _gamma_workloads(args.n_sub)
+    else:
+        ws = _allk_workloads(args.n_sub, args.sectors)
     J = ws[0].J
     reps = max(args.hv_reps, 1)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -220,10 +241,11 @@ def bench_allk(args):
         "vs_baseline": None,
         "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": "triangular36_allk", "n_sectors": len(ws),
+        "config": {"workload": args.workload, "n_sectors": len(ws),
                    "batch": tuned["batch"] if tuned else args.batch,
-                   "description": f"Heisenberg triangular 36 (6,0)x(0,6), 36 T, {len(ws)} momentum sectors "
-                                  f"({args.sectors}), Sz=0",
+                   "description": "Heisenberg triangular 36 (6,0)x(0,6), "
+                                  + BATCHED_WORKLOADS[args.workload].format(n=len(ws), which=args.sectors)
+                                  + ", Sz=0",
                    "shared_rows": info["dim"] if info else 0, "n_sublat": info["n_sublat"] if info else 0,
                    "parallelism": "1 GPU"},
         "batched_hv_ms": hv_ms,
@@ -295,7 +317,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs an MI355X GPU")
     torch.cuda.set_device(0)
-    if args.workload == "triangular36_allk":
+    if args.workload in BATCHED_WORKLOADS:
         return bench_allk(args)
     w, desc = _workload(args.workload, args.n_sub)
     tuning = dict(limits_bits=args.limits_bits, index_mode=args.index_mode, block_threads=args.block_threads,

@@ -207,6 +207,7 @@ static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, co
     }
     b->staged = two_stage_ok && (b->tuning.search_mode == ED_SEARCH_TWO_STAGE ||
                                  (b->tuning.search_mode == 0 && b->mean_candidates >= kTwoStageMinCandidates));
+    dm.staged = b->staged;
     rc = ed::launch_basis_build(b, stream);
     if (rc) {
         ed_free_basis(b);
@@ -383,6 +384,8 @@ static int sturm_count(int m, const double *a, const double *b2, double x)
 
 /* ---- batched sectors ---------------------------------------------------- */
 
+static constexpr size_t kChiLdsMaxBytes = 32768;   // largest character table staged in LDS
+
 int ed_build_multi(const ed_lattice_t *lat, const ed_group_t *grp, int32_t n_sectors, const ed_irrep_t *irreps,
                    int32_t n_up, const ed_tuning_t *tuning, void *stream, ed_multi_t **out)
 {
@@ -410,7 +413,12 @@ int ed_build_multi(const ed_lattice_t *lat, const ed_group_t *grp, int32_t n_sec
     ed_multi *mb = new (std::nothrow) ed_multi();
     if (!mb) return set_error(ED_ERR_OOM, "host allocation");
     mb->K = n_sectors;
-    const uint32_t reserve = (uint32_t)(((size_t)ng * n_sectors * 16 + 15) & ~(size_t)15);
+    // the character table [ng][K] is staged in LDS beside the lookup tables
+    // when it is small; a large one (big groups, many sectors) is read from
+    // HBM through the caches instead
+    const size_t chi_bytes = (size_t)ng * n_sectors * 16;
+    mb->chi_in_lds = chi_bytes <= kChiLdsMaxBytes;
+    const uint32_t reserve = mb->chi_in_lds ? (uint32_t)((chi_bytes + 15) & ~(size_t)15) : 0u;
     rc = build_basis_common(lat, grp, &trivial, n_up, &tn, reserve, stream, &mb->base);
     if (rc) {
         delete mb;

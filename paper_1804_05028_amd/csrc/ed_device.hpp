@@ -51,6 +51,7 @@ struct Ctx {
     const BondLds *bonds;
     const uint16_t *rank;
     const uint16_t *pos1;        // two-stage search: source block at position 1 | its state bit offset << 8
+    int staged;                  // pos1 is staged
 };
 
 __device__ __forceinline__ void lds_copy(char *dst, const void *src, uint32_t bytes)
@@ -85,6 +86,7 @@ __device__ __forceinline__ Ctx<AT> stage(const DevModel &dm, char *lds)
     c.bonds = (const BondLds *)(lds + dm.off_bonds);
     c.rank = (const uint16_t *)(lds + dm.off_rank);
     c.pos1 = (const uint16_t *)(lds + dm.off_pos1);
+    c.staged = dm.staged;
     return c;
 }
 
@@ -350,6 +352,22 @@ constexpr int kStagedFlag = 128;   // NSC bit selecting the two-stage search
 // NSC = NS * 8 + NC: sublattices and chunks fixed at compile time (0 = read
 // them at run time; NC = 0 with NS > 0 fixes only the sublattice count);
 // NSC + kStagedFlag selects the two-stage search (2 to 4 sublattices)
+// The same choice made at run time (a uniform branch on the staged flag),
+// for kernels that would otherwise need twice the template instances;
+// STAGED = false leaves the two-stage code out (same results, fewer
+// registers).
+template <typename AT, int NSC, bool STAGED>
+__device__ __forceinline__ uint64_t rep_search_rt(const Ctx<AT> &c, uint64_t s, uint32_t &g)
+{
+    constexpr int NS = (NSC & 127) / 8, NC = NSC % 8;
+    if constexpr (STAGED && NS >= 2 && NS <= 4) {
+        if (c.staged) return find_rep_staged<AT, NS, NC>(c, s, g);
+    }
+    if (NS > 0) return find_rep_ns<AT, (NS > 0 ? NS : 1), NC>(c, s, g);
+    uint32_t mv;
+    return find_rep(c, s, g, mv);
+}
+
 template <typename AT, int NSC>
 __device__ __forceinline__ uint64_t rep_search(const Ctx<AT> &c, uint64_t s, uint32_t &g)
 {

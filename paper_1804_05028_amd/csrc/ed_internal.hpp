@@ -77,6 +77,7 @@ struct DevModel {
     int n_div;
     int chunk_bits, n_chunks;
     int act_bytes;             // 1, 2 or 4 bytes per action-table entry
+    int staged;                // the pos1 table is staged: two-stage search available
     const char *blob;
     uint32_t off_rep, off_sym, off_act, off_shift, off_chi, off_div, off_divval, off_bonds, off_rank,
         off_pos1, lds_total;
@@ -146,6 +147,7 @@ struct ed_multi {
     void *chi_dev = nullptr;       // [ng][K] double2 (owned by base)
     std::vector<int64_t> dims;     // [K]
     uint32_t lds_chi_off = 0;      // LDS byte offset of the staged character table
+    bool chi_in_lds = true;        // else the kernel reads chi_dev through the caches
     double build_ms = 0.0;
     int grid_blocks = 0;
     // Lanczos workspace, kept between calls

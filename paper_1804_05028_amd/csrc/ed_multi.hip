@@ -28,7 +28,7 @@ struct MultiDev {
     const uint64_t *masks;    // [dim]
     const double2 *chi;       // [ng][K] in HBM
     uint32_t chi_off;         // LDS byte offset of the staged copy
-    uint32_t chi_bytes;
+    uint32_t chi_bytes;       // bytes staged in LDS (0: read chi from HBM)
 };
 
 // per-sector Lanczos state
@@ -121,8 +121,16 @@ __device__ __forceinline__ void cmac(double &ar, double &ai, double amp, double2
 // in stats[0..K), shared kept terms in stats[K], dropped lookups in
 // stats[K+1].
 // ---------------------------------------------------------------------------
+// threads per block: 512 where a lane holds more than 4 sectors alone or more
+// than 8 on a split row, so that the registers of one wave may exceed 128
+template <int KB, int SPLIT>
+constexpr int multi_block_bound()
+{
+    return (KB > 8 || (SPLIT == 1 && KB == 8)) ? 512 : 1024;
+}
+
 template <typename AT, int NS, int KB, int MODE, int SPLIT>
-__global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
+__global__ void __launch_bounds__((multi_block_bound<KB, SPLIT>()))
     k_apply_multi(DevModel dm, DevBasis db, MultiDev md, const double2 *__restrict__ x, double2 *y,
                   const double2 *vprev, const MlzSector *__restrict__ sec, double *stats, double jsq)
 {
@@ -138,6 +146,11 @@ __global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
     const int64_t D = db.dim;
     const uint64_t smask = (1ull << db.slot_log2) - 1ull;
     const int lane = threadIdx.x & (kWave - 1);
+    // the two-stage search is compiled in where registers allow it without
+    // spilling; elsewhere the one-stage search gives the same results
+    constexpr bool kStagedFits = KB <= 4 || (SPLIT > 1 && KB <= 8);
+    // the same instances can read a character table kept in HBM
+    constexpr bool kChiHbm = kStagedFits;
     // this lane's row within the wave's group of rows, and its sectors
     constexpr int kRows = kWave / SPLIT;
     const int rl = lane / SPLIT;
@@ -186,7 +199,7 @@ __global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
             const BondLds bd = c.bonds[pop_bond(am)];
             anti_sum += bd.jzhalf;
             jh_nx = bd.jhalf;
-            r_nx = rep_search<AT, NS>(c, s ^ bd.mask, g_nx);
+            r_nx = rep_search_rt<AT, NS, kStagedFits>(c, s ^ bd.mask, g_nx);
             sl_nx = slot_of_state(r_nx, db.slot_log2);
             q_nx = load_slot<false>(db.slots, sl_nx);
         }
@@ -218,7 +231,7 @@ __global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
                 const BondLds bd = c.bonds[pop_bond(am)];
                 anti_sum += bd.jzhalf;
                 jh_nx = bd.jhalf;
-                r_nx = rep_search<AT, NS>(c, s ^ bd.mask, g_nx);
+                r_nx = rep_search_rt<AT, NS, kStagedFits>(c, s ^ bd.mask, g_nx);
                 sl_nx = slot_of_state(r_nx, db.slot_log2);
                 q_nx = load_slot<false>(db.slots, sl_nx);
             }
@@ -233,19 +246,26 @@ __global__ void __launch_bounds__(KB > 8 ? 512 : 1024)
                 continue;
             }
             const double amp = jh * rs_i * c.div_sqrt[q.x >> kNormShift];
-            const double2 *ch = chik + (size_t)g * K + koff;
-            if (kPre) {
+            auto accumulate = [&](const double2 *ch) {
+                if (kPre) {
 #pragma unroll
-                for (int k = 0; k < (kPre ? KB : 1); ++k) {
-                    if (k < KL) cmac(ar[k], ai[k], amp, ch[k], xv[k]);
-                }
-            } else {
-                const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K + koff;
+                    for (int k = 0; k < (kPre ? KB : 1); ++k) {
+                        if (k < KL) cmac(ar[k], ai[k], amp, ch[k], xv[k]);
+                    }
+                } else {
+                    const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K + koff;
 #pragma unroll
-                for (int k = 0; k < KB; ++k) {
-                    if (k < KL && ((mij >> k) & 1ull)) cmac(ar[k], ai[k], amp, ch[k], xj[k]);
+                    for (int k = 0; k < KB; ++k) {
+                        if (k < KL && ((mij >> k) & 1ull)) cmac(ar[k], ai[k], amp, ch[k], xj[k]);
+                    }
                 }
-            }
+            };
+            // characters chi_k(g) of this lane's sectors: the LDS copy, or
+            // HBM in the instances with registers for a second accumulate path
+            if (kChiHbm && md.chi_bytes == 0)
+                accumulate(md.chi + (size_t)g * K + koff);
+            else
+                accumulate(chik + (size_t)g * K + koff);
         }
         if (MODE == 1 || !row_ok) continue;
         const double d = jsq - anti_sum;
@@ -468,14 +488,14 @@ static int multi_launch_impl(const ed_multi *mb, const void *x, void *y, const v
 {
     const ed_basis *b = mb->base;
     auto kern = k_apply_multi<AT, NS, KB, MODE, SPLIT>;
-    const int bound = KB > 8 ? 512 : 1024;
+    const int bound = multi_block_bound<KB, SPLIT>();
     int threads = b->tuning.block_threads > 0 ? std::min(b->tuning.block_threads, bound) : bound;
     MultiDev md;
     md.K = mb->K;
     md.masks = mb->masks;
     md.chi = (const double2 *)mb->chi_dev;
     md.chi_off = mb->lds_chi_off;
-    md.chi_bytes = (uint32_t)((size_t)b->t.ng * mb->K * 16);
+    md.chi_bytes = mb->chi_in_lds ? (uint32_t)((size_t)b->t.ng * mb->K * 16) : 0u;
     const size_t lds = (size_t)md.chi_off + md.chi_bytes;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess || per_cu < 1)
@@ -494,12 +514,17 @@ static int multi_launch_impl(const ed_multi *mb, const void *x, void *y, const v
 // lanes per row of the batched H.v: the caller's choice, else 1 lane for up
 // to 2 sectors, 2 lanes for up to 8 and 4 lanes above (measured on the
 // 36-site triangular momentum sectors: each lane then holds at most 4
-// sectors for K <= 16 and prefetches their next amplitudes)
+// sectors for K <= 16 and prefetches their next amplitudes); raised where
+// the character table lives in HBM (see kChiHbm)
 int multi_lanes_per_row(const ed_multi *mb)
 {
-    const int t = mb->base->tuning.lanes_per_row;
-    if (t > 0) return t;
-    return mb->K <= 2 ? 1 : (mb->K <= 8 ? 2 : 4);
+    const int K = mb->K;
+    int t = mb->base->tuning.lanes_per_row;
+    if (t <= 0) t = K <= 2 ? 1 : (K <= 8 ? 2 : 4);
+    // a character table read from HBM needs an instance with at most 4
+    // sectors per lane, or 8 per lane on a split row
+    if (!mb->chi_in_lds) t = std::max(t, K <= 4 ? 1 : (K <= 16 ? 2 : 4));
+    return t;
 }
 
 template <int MODE, typename AT, int NS>
@@ -531,11 +556,13 @@ static int multi_launch(const ed_multi *mb, const void *x, void *y, const void *
                         double jsq, hipStream_t st)
 {
     const ed_basis *b = mb->base;
-    // four sublattices with one or two chunks: search loops fixed at compile time
-    const int nsc = (MODE == 0 && b->dm.ns == 4 && b->dm.n_chunks <= 2) ? 32 + b->dm.n_chunks : 0;
+    // four sublattices with one to three chunks: search loops fixed at compile
+    // time (three chunks for 2-byte entries only)
+    const int nsc = (MODE == 0 && b->dm.ns == 4 && b->dm.n_chunks <= 3) ? 32 + b->dm.n_chunks : 0;
     if (table_width(b) == 2) {
         if (nsc == 33) return multi_launch_kb<MODE, uint16_t, 33>(mb, x, y, vprev, sec, stats, jsq, st);
         if (nsc == 34) return multi_launch_kb<MODE, uint16_t, 34>(mb, x, y, vprev, sec, stats, jsq, st);
+        if (nsc == 35) return multi_launch_kb<MODE, uint16_t, 35>(mb, x, y, vprev, sec, stats, jsq, st);
         return multi_launch_kb<MODE, uint16_t, 0>(mb, x, y, vprev, sec, stats, jsq, st);
     }
     if (table_width(b) == 4) {

@@ -44,3 +44,16 @@ def test_traffic_is_reported_only_for_the_profiled_kernel():
     digest, fetch, write = bench.MEASURED_TRAFFIC[key]
     t = bench.measured_traffic(key)
     assert t is None or (bench.kernel_digest() == digest and t == fetch + write)
+
+
+def test_gamma_irreps_workload():
+    import bench
+    from paper_1804_05028_amd import _lib as L
+    ws = bench._gamma_workloads(4)
+    assert len(ws) == 8 and len({w.name for w in ws}) == 8
+    chis = [tuple(np.round(w.chi.real, 6)) for w in ws]
+    assert len(set(chis)) == 8
+    for w in ws:
+        c = w.cluster
+        L.ed_validate(L.ModelArrays(c.n_sites, c.bonds, c.n_sublat, c.perm, c.flip, w.chi), w.n_up)
+    assert set(bench.BATCHED_WORKLOADS) == {"triangular36_allk", "triangular36_gamma"}

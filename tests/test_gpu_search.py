@@ -109,3 +109,40 @@ def test_automatic_choice_follows_the_candidate_count():
             assert info["search_mode"] == want, (w.name, info["mean_candidates"])
         finally:
             b.close()
+
+
+def test_batched_two_stage_matches_one_stage_and_oracle():
+    """The batched kernel runs the two-stage search through a run-time flag.
+    16 sectors of the 4x4 full space group (Gamma and M, every 1-D point-group
+    irrep, both flip parities): their 256 x 16 character table exceeds the LDS
+    share and is read from HBM."""
+    from ed_inputs import lattice as lat
+    ed = _ed()
+    c = lat.square((4, 0), (0, 4), rotations=True, mirrors=True, spin_flip=True, superlattice=wl.SQ_2X2,
+                   name="square16full")
+    U, det = lat.momenta(c)
+    ks = [0, U.index((det // 2, det // 2))]
+    pcs = lat.point_group_chars_1d(c.point_group)
+    ws = [wl.Workload("sq16full", c, lat.characters(c, k, p, f), 8, np.ones(c.n_bonds))
+          for k in ks for p in pcs for f in (1, -1)]
+    assert len(ws) == 16 and c.n_elems * len(ws) * 16 > 32768
+    ys, x, masks = {}, None, None
+    for mode in (ONE, TWO):
+        mb = ed.MultiBasis.from_workloads(ws, {"search_mode": mode})
+        try:
+            if x is None:
+                re = vec.normal_vector(mb.dim * mb.K, seed=17, normalise=False)
+                x = (re + 0.25j * re[::-1]).reshape(mb.dim, mb.K)
+                masks = mb.masks()
+            ys[mode] = mb.apply(ws[0].J, torch.as_tensor(x).cuda()).cpu().numpy()
+        finally:
+            mb.close()
+    assert np.array_equal(ys[ONE], ys[TWO])
+    for k, w in enumerate(ws):
+        sel = ((masks >> np.uint64(k)) & np.uint64(1)).astype(bool)
+        if not sel.any():
+            continue
+        m = bf.Model.from_workload(w)
+        st, stab = bf.basis(m, w.n_up)
+        ref, _, _ = bf.apply(m, st, stab, x[sel, k])
+        assert np.linalg.norm(ys[TWO][sel, k] - ref) <= RTOL * np.linalg.norm(ref), k
