@@ -68,7 +68,8 @@ def measured_traffic(key):
     return rec[1] + rec[2] if kernel_digest() == rec[0] else None
 
 
-AUTOTUNE_NSUB = {"square40_j1j2": [4, 5], "square40_j1j2j3": [4, 5], "triangular36": [3, 4], "square32_disorder": [4, 8], "square16": [2, 4]}
+AUTOTUNE_NSUB = {"square40_j1j2": [4, 5], "square40_j1j2j3": [4, 5], "triangular36": [3, 4], "triangular36_k1": [4],
+                 "square32_disorder": [4, 8], "square16": [2, 4]}
 
 
 def _workload(name, n_sub):
@@ -87,6 +88,9 @@ def _workload(name, n_sub):
         w = wl.Workload(w.name, w.cluster, w.chi, w.n_up, lat.orbit_mean(w.J, lat.bond_orbits(w.cluster)),
                         w.description)
         return w, "Heisenberg square 32 (4,4)x(-4,4), 32T, k=0, orbit-averaged J_b ~ U(0.8,1.2)"
+    if name == "triangular36_k1":
+        return (wl.triangular_36_momentum(1, n_sub=n_sub or 4),
+                "Heisenberg triangular 36 (6,0)x(0,6), 36 T, momentum sector k=1 (complex), Sz=0")
     if name == "square16":
         return wl.square_4x4(n_sub=n_sub or 4), "Heisenberg square 16 (4x4), 16T, k=0, Sz=0"
     raise SystemExit(f"unknown workload {name}")
