@@ -80,3 +80,27 @@ def test_automatic_lanes_per_row():
             assert mb.info()["lanes_per_row"] == want, len(ws)
         finally:
             mb.close()
+
+
+def test_lane_count_raised_for_character_tables_in_hbm():
+    """16 full-group sectors of the 4x4 lattice carry a 64 KB character table,
+    which is read from HBM; a forced single lane is raised to 2, and the
+    result equals that of the automatic choice bit for bit."""
+    ed = _ed()
+    c = lat.square((4, 0), (0, 4), rotations=True, mirrors=True, spin_flip=True, superlattice=wl.SQ_2X2,
+                   name="square16full")
+    U, det = lat.momenta(c)
+    ks = [0, U.index((det // 2, det // 2))]
+    pcs = lat.point_group_chars_1d(c.point_group)
+    ws = [wl.Workload("sq16full", c, lat.characters(c, k, p, f), 8, np.ones(c.n_bonds))
+          for k in ks for p in pcs for f in (1, -1)]
+    ys = {}
+    for lanes in (1, 0):
+        mb = ed.MultiBasis.from_workloads(ws, {"lanes_per_row": lanes})
+        try:
+            assert mb.info()["lanes_per_row"] == (2 if lanes == 1 else 4)
+            x = _x(mb.dim, mb.K, 41)
+            ys[lanes] = mb.apply(ws[0].J, torch.as_tensor(x).cuda()).cpu().numpy()
+        finally:
+            mb.close()
+    assert np.array_equal(ys[1], ys[0])
