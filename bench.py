@@ -48,7 +48,7 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_05028_amd", "csrc", f)
 MEASURED_TRAFFIC = {
     # (workload, n_sublat, index, chunk_bits): (kernel sha256, fetch bytes, write bytes)
     ("square40_j1j2", 4, "hash-slot", 5): (
-        "980929bd756a670394969bd398ebc2ae5e0b3bdf50f61d68ee2303d30235b447", 4.93171e+12, 3.44728e+09),
+        "9e4cb81045d154e76905eaaf774054a58af28df30bfe3073105bf9c40a49fc06", 4.93166e+12, 3.44728e+09),
 }
 
 

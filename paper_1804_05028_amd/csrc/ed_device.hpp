@@ -309,8 +309,10 @@ __device__ __forceinline__ uint64_t find_rep_staged(const Ctx<AT> &c, uint64_t s
             }
             continue;
         }
-        // stage 1: the position-1 block of every candidate
+        // stage 1: the position-1 block of every candidate (two candidates
+        // per iteration, so that their dependent LDS reads overlap)
         uint32_t min1 = 0xFFFFFFFFu, keep = 0;
+#pragma unroll 2
         for (uint32_t k = 0; k < cnt; ++k) {
             const uint32_t ent = c.sym[off + 1 + k];
             const uint32_t u = (ent >> 16) & 0x7FFFu;
