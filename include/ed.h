@@ -103,7 +103,10 @@ typedef struct {
     int32_t table_entry_bytes; /* 1, 2 or 4 bytes per symmetry-action entry (wide ones carry the block
                                   position); 0 = automatic                                              */
     int32_t search_mode;    /* representative search of the index_mode 0 H.v and Lanczos kernels
-                               (the batched and adjoint kernels always run the one-stage search):
+                               and of the batched kernel (in its instances with at most 4 sectors
+                               per lane, or 8 on split rows, and compile-time search loops; the
+                               others and the adjoint kernel run the one-stage search, which gives
+                               the same results):
                                ED_SEARCH_ONE_STAGE = assemble the full image of every candidate;
                                ED_SEARCH_TWO_STAGE = image the block landing below the top block
                                first and assemble only the candidates minimising it (2 to 4
