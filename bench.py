@@ -48,7 +48,7 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_05028_amd", "csrc", f)
 MEASURED_TRAFFIC = {
     # (workload, n_sublat, index, chunk_bits): (kernel sha256, fetch bytes, write bytes)
     ("square40_j1j2", 4, "hash-slot", 5): (
-        "9e4cb81045d154e76905eaaf774054a58af28df30bfe3073105bf9c40a49fc06", 4.93166e+12, 3.44728e+09),
+        "cbbaaaec8104eb43d71753dc667cf74c7d6de096e0a6734731fe717853040e9c", 4.93176e+12, 3.44728e+09),
 }
 
 
@@ -295,6 +295,9 @@ def main():
     ap.add_argument("--chunk-bits", type=int, default=0)
     ap.add_argument("--hash-load-pct", type=int, default=0)
     ap.add_argument("--table-entry-bytes", type=int, default=0)
+    ap.add_argument("--search-mode", type=int, default=0, help="1 one-stage, 2 two-stage representative search")
+    ap.add_argument("--lanczos-direct", action="store_true",
+                    help="launch the Lanczos step kernels directly instead of replaying a HIP graph")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--hv-reps", type=int, default=5, help="extra timed H.v launches for the roofline")
@@ -326,14 +329,15 @@ def main():
     w, desc = _workload(args.workload, args.n_sub)
     tuning = dict(limits_bits=args.limits_bits, index_mode=args.index_mode, block_threads=args.block_threads,
                   blocks_per_cu=args.blocks_per_cu, chunk_bits=args.chunk_bits, hash_load_pct=args.hash_load_pct,
-                  table_entry_bytes=args.table_entry_bytes)
+                  table_entry_bytes=args.table_entry_bytes, search_mode=args.search_mode,
+                  lanczos_direct=int(args.lanczos_direct))
     tuned = None
     if args.autotune:
         from paper_1804_05028_amd import autotune as at
         best, results = at.autotune(lambda ns: _workload(args.workload, ns)[0], AUTOTUNE_NSUB[args.workload],
                                     reps=2, log=lambda m: print(m, file=sys.stderr, flush=True))
         w, desc = _workload(args.workload, best["n_sub"])
-        tuning = dict(best["tuning"])
+        tuning = dict(best["tuning"], lanczos_direct=int(args.lanczos_direct))
         tuned = {"n_sub": best["n_sub"], "tuning": tuning, "hv_ms": best["hv_ms"],
                  "trials": [(r["n_sub"], r["tuning"], r.get("hv_ms"), r.get("error")) for r in results]}
     print(f"[bench] building basis: {desc}", file=sys.stderr, flush=True)

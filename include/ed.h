@@ -118,6 +118,8 @@ typedef struct {
                                When |G| K 16 bytes of characters exceed 32 KB they are read from
                                HBM, and the lane count is raised to at least 2 for K > 4 and 4
                                for K > 16 (ed_multi_info reports the count used)                */
+    int32_t lanczos_direct; /* ed_lanczos: 1 = launch each step's kernels directly; 0 = capture the
+                               step once per buffer assignment in a HIP graph and replay it        */
 } ed_tuning_t;
 
 #define ED_SEARCH_ONE_STAGE 1

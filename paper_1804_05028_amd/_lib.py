@@ -47,7 +47,7 @@ class ed_tuning_t(ctypes.Structure):
                 ("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("chunk_bits", ctypes.c_int32), ("hash_load_pct", ctypes.c_int32),
                 ("table_entry_bytes", ctypes.c_int32), ("search_mode", ctypes.c_int32),
-                ("lanes_per_row", ctypes.c_int32)]
+                ("lanes_per_row", ctypes.c_int32), ("lanczos_direct", ctypes.c_int32)]
 
 
 ED_SEARCH_ONE_STAGE = 1
@@ -248,7 +248,7 @@ def _tuning(tuning):
                        int(tuning.get("block_threads", 0)), int(tuning.get("blocks_per_cu", 0)),
                        int(tuning.get("chunk_bits", 0)), int(tuning.get("hash_load_pct", 0)),
                        int(tuning.get("table_entry_bytes", 0)), int(tuning.get("search_mode", 0)),
-                       int(tuning.get("lanes_per_row", 0)))
+                       int(tuning.get("lanes_per_row", 0)), int(tuning.get("lanczos_direct", 0)))
 
 
 def ed_build_basis(arrays: ModelArrays, n_up, tuning=None, stream=None):

@@ -170,7 +170,8 @@ static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, co
          b->tuning.table_entry_bytes != 4) ||
         b->tuning.search_mode < 0 || b->tuning.search_mode > ED_SEARCH_TWO_STAGE ||
         (b->tuning.lanes_per_row != 0 && b->tuning.lanes_per_row != 1 && b->tuning.lanes_per_row != 2 &&
-         b->tuning.lanes_per_row != 4)) {
+         b->tuning.lanes_per_row != 4) ||
+        (b->tuning.lanczos_direct != 0 && b->tuning.lanczos_direct != 1)) {
         delete b;
         return set_error(ED_ERR_ARG, "tuning fields out of range");
     }

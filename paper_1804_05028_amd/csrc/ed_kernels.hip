@@ -1343,27 +1343,94 @@ int run_lanczos(const ed_basis *bc, const double *J, const double *Jz, const voi
         hipLaunchKernelGGL(k_norm2_partial, dim3(vgrid), dim3(kVecThreads), 0, st, (const double *)v0, nd, partials);
         hipLaunchKernelGGL(k_scale_by_norm, dim3(vgrid), dim3(kVecThreads), 0, st, (const double *)v0, B, nd,
                            (const double *)partials, vgrid);
-        double *vprev = A, *v = B, *w = C;
-        for (int step = 0; step < n_steps; ++step) {
-            rc = pack_input(b, v, st);
-            if (rc) return rc;
-            rc = apply_dispatch<2>(b, v, w, vprev, partials, nullptr, lz, jsq, st);
-            if (rc) return rc;
-            hipLaunchKernelGGL(k_lz_alpha, dim3(1), dim3(64), 0, st, lz, (const double *)partials, np_apply, ahist);
-            hipLaunchKernelGGL(k_lz_update, dim3(vgrid), dim3(kVecThreads), 0, st, w, (const double *)v, nd, partials,
+        // one step: pack v into the slots, w = H v - beta v_prev with <v, w>
+        // partials, alpha, w -= alpha v (and psi += s_j v), beta, v_prev <-
+        // w / beta.  Every quantity that changes between steps lives on the
+        // device (the step index in lz), so the step can be captured once per
+        // buffer assignment and replayed.
+        auto step_kernels = [&](double *vprev_, double *v_, hipStream_t s_) -> int {
+            int r = pack_input(b, v_, s_);
+            if (r) return r;
+            r = apply_dispatch<2>(b, v_, C, vprev_, partials, nullptr, lz, jsq, s_);
+            if (r) return r;
+            hipLaunchKernelGGL(k_lz_alpha, dim3(1), dim3(64), 0, s_, lz, (const double *)partials, np_apply, ahist);
+            hipLaunchKernelGGL(k_lz_update, dim3(vgrid), dim3(kVecThreads), 0, s_, C, (const double *)v_, nd, partials,
                                (const LzState *)lz, psi, (const double *)svec);
-            hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(64), 0, st, lz, (const double *)partials, vgrid, bhist, n_steps,
-                               1e-12);
-            hipLaunchKernelGGL(k_lz_normalize, dim3(vgrid), dim3(kVecThreads), 0, st, (const double *)w, vprev, nd,
+            hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(64), 0, s_, lz, (const double *)partials, vgrid, bhist,
+                               n_steps, 1e-12);
+            hipLaunchKernelGGL(k_lz_normalize, dim3(vgrid), dim3(kVecThreads), 0, s_, (const double *)C, vprev_, nd,
                                (const LzState *)lz);
-            hipLaunchKernelGGL(k_lz_shift_beta, dim3(1), dim3(64), 0, st, lz);
-            std::swap(vprev, v);   // the new v was written over vprev
+            hipLaunchKernelGGL(k_lz_shift_beta, dim3(1), dim3(64), 0, s_, lz);
+            const hipError_t e = hipGetLastError();
+            return e == hipSuccess ? ED_OK : set_error(ED_ERR_HIP, "Lanczos step launch: %s", hipGetErrorString(e));
+        };
+        // the buffer roles alternate: (v_prev, v) = (A, B), then (B, A)
+        const bool use_graph = !b->tuning.lanczos_direct;
+        hipGraphExec_t exec[2] = {nullptr, nullptr};
+        hipStream_t cap = nullptr;
+        auto release = [&]() {
+            for (auto &x : exec)
+                if (x) (void)hipGraphExecDestroy(x);
+            if (cap) (void)hipStreamDestroy(cap);
+            exec[0] = exec[1] = nullptr;
+            cap = nullptr;
+        };
+        if (use_graph) {
+            if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+                (void)hipGetLastError();
+                return set_error(ED_ERR_HIP, "capture stream");
+            }
+            for (int p = 0; p < 2; ++p) {
+                hipGraph_t graph = nullptr;
+                if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                    (void)hipGetLastError();
+                    release();
+                    return set_error(ED_ERR_HIP, "begin capture");
+                }
+                rc = step_kernels(p == 0 ? A : B, p == 0 ? B : A, cap);
+                const hipError_t e = hipStreamEndCapture(cap, &graph);
+                if (rc || e != hipSuccess) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    release();
+                    return rc ? rc : set_error(ED_ERR_HIP, "end capture: %s", hipGetErrorString(e));
+                }
+                const hipError_t ei = hipGraphInstantiate(&exec[p], graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (ei != hipSuccess) {
+                    release();
+                    return set_error(ED_ERR_HIP, "graph instantiate: %s", hipGetErrorString(ei));
+                }
+            }
+        }
+        for (int step = 0; step < n_steps; ++step) {
+            const int p = step & 1;
+            if (use_graph) {
+                const hipError_t e = hipGraphLaunch(exec[p], st);
+                if (e != hipSuccess) {
+                    release();
+                    return set_error(ED_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+                }
+            } else {
+                rc = step_kernels(p == 0 ? A : B, p == 0 ? B : A, st);
+                if (rc) return rc;
+            }
             if ((step & 15) == 15) {
                 LzState hs;
-                HIP_TRY(hipMemcpyAsync(&hs, lz, sizeof hs, hipMemcpyDeviceToHost, st));
-                HIP_TRY(hipStreamSynchronize(st));
+                if (hipMemcpyAsync(&hs, lz, sizeof hs, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess) {
+                    release();
+                    return set_error(ED_ERR_HIP, "Lanczos state readback");
+                }
                 if (hs.done) break;
             }
+        }
+        if (use_graph) {
+            // the replays are ordered on st; the executables may go once they finish
+            if (hipStreamSynchronize(st) != hipSuccess) {
+                release();
+                return set_error(ED_ERR_HIP, "Lanczos replay");
+            }
+            release();
         }
         LzState hs;
         HIP_TRY(hipMemcpyAsync(&hs, lz, sizeof hs, hipMemcpyDeviceToHost, st));

@@ -271,3 +271,4 @@ def test_tuning_modes_are_validated_before_any_device_work():
     _expect("ED_ERR_ARG", lambda: L.ed_build_basis(arrays, w.n_up, {"search_mode": 3}))
     _expect("ED_ERR_ARG", lambda: L.ed_build_basis(arrays, w.n_up, {"search_mode": -1}))
     _expect("ED_ERR_ARG", lambda: L.ed_build_basis(arrays, w.n_up, {"lanes_per_row": 3}))
+    _expect("ED_ERR_ARG", lambda: L.ed_build_basis(arrays, w.n_up, {"lanczos_direct": 2}))
