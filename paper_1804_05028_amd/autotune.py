@@ -139,8 +139,7 @@ def autotune_batched(workloads, batches=(4, 8, 12, 16), lanes=(1, 2, 4), reps=1,
     J = workloads[0].J
     best_of = {}   # group size -> (ms, lanes)
     trials = []
-    sizes = sorted({min(b, n) for b in batches} | {n % b for b in batches if n % b and b < n})
-    for K in sizes:
+    for K in schedule_sizes(n, batches):
         for L in lanes:
             mb = ed.MultiBasis.from_workloads(workloads[:K], {"lanes_per_row": L})
             try:
@@ -153,13 +152,29 @@ def autotune_batched(workloads, batches=(4, 8, 12, 16), lanes=(1, 2, 4), reps=1,
                 log(f"[autotune] K={K} lanes_per_row={L}: {ms:.1f} ms")
             if K not in best_of or ms < best_of[K][0]:
                 best_of[K] = (ms, L)
+    return dict(plan_schedule(n, batches, best_of), trials=trials)
+
+
+def schedule_sizes(n, batches):
+    """Group sizes the schedules with these batch sizes need for n sectors
+    (full groups and remainders)."""
+    return sorted({min(b, n) for b in batches} | {n % b for b in batches if n % b and b < n})
+
+
+def plan_schedule(n, batches, best_of):
+    """Cheapest schedule of consecutive groups for n sectors.
+
+    best_of[size] = (ms, lanes_per_row) for every size in schedule_sizes.
+    Returns {"batch", "groups": [(first, size, lanes_per_row)], "est_ms"};
+    ties go to the smaller batch size.
+    """
     plans = []
     for b in batches:
         b = min(b, n)
         groups = [(i, min(b, n - i)) for i in range(0, n, b)]
         plans.append((sum(best_of[k][0] for _, k in groups), b, groups))
     est, b, groups = min(plans)
-    return {"batch": b, "groups": [(i, k, best_of[k][1]) for i, k in groups], "est_ms": est, "trials": trials}
+    return {"batch": b, "groups": [(i, k, best_of[k][1]) for i, k in groups], "est_ms": est}
 
 
 def speedup_table(results):
@@ -169,4 +184,5 @@ def speedup_table(results):
     return [(r["n_sub"], r["tuning"], r["hv_ms"], r["hv_ms"] / b) for r in timed]
 
 
-__all__ = ["autotune", "autotune_batched", "autotune_decompositions", "default_candidates", "speedup_table"]
+__all__ = ["autotune", "autotune_batched", "autotune_decompositions", "default_candidates", "plan_schedule",
+           "schedule_sizes", "speedup_table"]
