@@ -113,8 +113,7 @@ typedef struct {
                                sublattices, else ED_ERR_UNSUPPORTED); 0 = two-stage when a host
                                sample of the search averages at least 3 candidates               */
     int32_t lanes_per_row;  /* batched H.v (ed_build_multi): 1, 2 or 4 lanes share a row, each
-                               running the row's searches and holding ceil(K / lanes) of its
-                               sectors; 0 = 1 lane for K <= 2, 2 lanes for K <= 8, else 4.
+                               running the row's searches and holding every lanes-th sector; 0 = 1 lane for K <= 2, 2 lanes for K <= 8, else 4.
                                When |G| K 16 bytes of characters exceed 32 KB they are read from
                                HBM, and the lane count is raised to at least 2 for K > 4 and 4
                                for K > 16 (ed_multi_info reports the count used)                */

@@ -112,21 +112,22 @@ __device__ __forceinline__ void cmac(double &ar, double &ai, double amp, double2
 // ---------------------------------------------------------------------------
 // Batched H.v.  KB is the compile-time bound of the sector loop.  SPLIT lanes
 // share a row: each runs the row's searches and probes (same addresses, so
-// the requests of a load instruction merge) and owns ceil(K / SPLIT) of its
-// sectors, which divides the per-lane accumulator and amplitude registers by
-// SPLIT and raises the number of waves a compute unit holds.
+// the requests of a load instruction merge) and owns every SPLIT-th sector
+// (lane r: r, r + SPLIT, ...), which divides the per-lane accumulator and
+// amplitude registers by SPLIT and raises the number of waves a compute unit
+// holds; the lanes of a row read adjacent amplitudes in each instruction.
 // MODE 0: y = H x, or w = H v - beta_prev[k] vprev when vprev is given
 // (Lanczos; y may be vprev itself: each element is read and then written by
 // the same thread).  MODE 1 (SPLIT 1): per-sector term counts (D_k + kept_k)
 // in stats[0..K), shared kept terms in stats[K], dropped lookups in
 // stats[K+1].
 // ---------------------------------------------------------------------------
-// threads per block: 512 where a lane holds more than 4 sectors alone or more
-// than 8 on a split row, so that the registers of one wave may exceed 128
+// threads per block: 512 where a lane holds more than 4 sectors, so that the
+// registers of one wave may exceed 128 without spilling
 template <int KB, int SPLIT>
 constexpr int multi_block_bound()
 {
-    return (KB > 8 || (SPLIT == 1 && KB == 8)) ? 512 : 1024;
+    return KB >= 8 ? 512 : 1024;
 }
 
 template <typename AT, int NS, int KB, int MODE, int SPLIT>
@@ -154,9 +155,10 @@ __global__ void __launch_bounds__((multi_block_bound<KB, SPLIT>()))
     // this lane's row within the wave's group of rows, and its sectors
     constexpr int kRows = kWave / SPLIT;
     const int rl = lane / SPLIT;
-    const int KH = (K + SPLIT - 1) / SPLIT;
-    const int koff = (lane % SPLIT) * KH;
-    const int KL = max(min(K - koff, KH), 0);   // sectors of this lane: koff .. koff + KL - 1
+    // sectors of this lane: koff, koff + SPLIT, ... (KL of them), so that the
+    // lanes of a row read neighbouring amplitudes in each load instruction
+    const int koff = lane % SPLIT;
+    const int KL = koff < K ? (K - koff + SPLIT - 1) / SPLIT : 0;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t n_waves = (int64_t)gridDim.x * blockDim.x / kWave;
     double shared = 0.0, dropped = 0.0;
@@ -169,7 +171,7 @@ __global__ void __launch_bounds__((multi_block_bound<KB, SPLIT>()))
         const int64_t i = i0 + rl;
         const bool row_ok = i < D;
         const uint64_t e = row_ok ? db.states[i] : 0ull;
-        const uint64_t mi = row_ok ? md.masks[i] >> koff : 0ull;   // bit k: sector koff + k
+        const uint64_t mi = row_ok ? md.masks[i] : 0ull;
         const uint64_t s = e & kStateMask;
         const double rs_i = c.div_rsqrt[e >> kNormShift];
         if (MODE == 0) {
@@ -214,7 +216,7 @@ __global__ void __launch_bounds__((multi_block_bound<KB, SPLIT>()))
                 q = load_slot<false>(db.slots, sl);
             }
             const bool found = q.x != kEmpty;
-            const uint64_t mij = found ? (mi & (q.y >> (32 + koff))) : 0ull;
+            const uint64_t mij = found ? (mi & (q.y >> 32)) : 0ull;   // bit koff + SPLIT k: local sector k
             // the target's amplitudes are requested before the next term's
             // search, which hides their latency
             // registers allow holding the next row's amplitudes (split rows
@@ -225,7 +227,7 @@ __global__ void __launch_bounds__((multi_block_bound<KB, SPLIT>()))
                 const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K + koff;
 #pragma unroll
                 for (int k = 0; k < KB; ++k)
-                    xv[k] = (k < KL && ((mij >> k) & 1ull)) ? xj[k] : make_double2(0.0, 0.0);
+                    xv[k] = (k < KL && ((mij >> (koff + SPLIT * k)) & 1ull)) ? xj[SPLIT * k] : make_double2(0.0, 0.0);
             }
             if (term + 1 < n_terms) {
                 const BondLds bd = c.bonds[pop_bond(am)];
@@ -250,13 +252,13 @@ __global__ void __launch_bounds__((multi_block_bound<KB, SPLIT>()))
                 if (kPre) {
 #pragma unroll
                     for (int k = 0; k < (kPre ? KB : 1); ++k) {
-                        if (k < KL) cmac(ar[k], ai[k], amp, ch[k], xv[k]);
+                        if (k < KL) cmac(ar[k], ai[k], amp, ch[SPLIT * k], xv[k]);
                     }
                 } else {
                     const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K + koff;
 #pragma unroll
                     for (int k = 0; k < KB; ++k) {
-                        if (k < KL && ((mij >> k) & 1ull)) cmac(ar[k], ai[k], amp, ch[k], xj[k]);
+                        if (k < KL && ((mij >> (koff + SPLIT * k)) & 1ull)) cmac(ar[k], ai[k], amp, ch[SPLIT * k], xj[SPLIT * k]);
                     }
                 }
             };
@@ -275,18 +277,18 @@ __global__ void __launch_bounds__((multi_block_bound<KB, SPLIT>()))
         for (int k = 0; k < KB; ++k) {
             if (k < KL) {
                 double2 out = make_double2(0.0, 0.0);
-                if ((mi >> k) & 1ull) {
-                    const double2 xv = xi[k];
+                if ((mi >> (koff + SPLIT * k)) & 1ull) {
+                    const double2 xv = xi[SPLIT * k];
                     out.x = d * xv.x + ar[k];
                     out.y = d * xv.y + ai[k];
                     if (vprev) {
-                        const double bp = sec[koff + k].beta_prev;
-                        const double2 vp = vprev[(size_t)i * K + koff + k];
+                        const double bp = sec[koff + SPLIT * k].beta_prev;
+                        const double2 vp = vprev[(size_t)i * K + koff + SPLIT * k];
                         out.x -= bp * vp.x;
                         out.y -= bp * vp.y;
                     }
                 }
-                yi[k] = out;
+                yi[SPLIT * k] = out;
             }
         }
     }
