@@ -312,8 +312,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
-                                   "not an implemented path", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the H.v path runs on one GPU; sharding a sector over several GPUs "
+                                   "is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch

@@ -48,7 +48,7 @@ extern "C" {
 #define ED_ERR_NONINVARIANT_H (-6)         /* bonds or couplings not group invariant */
 #define ED_ERR_OOM (-7)                    /* device allocation failed              */
 #define ED_ERR_HIP (-8)                    /* a HIP runtime call failed             */
-#define ED_ERR_UNSUPPORTED (-9)            /* size outside what this build handles  */
+#define ED_ERR_UNSUPPORTED (-9)            /* size or layout the library does not handle */
 
 /*
  * Lattice: N sites, bonds, and the sublattice decomposition.
