@@ -25,7 +25,11 @@ class Basis:
 
     Parameters mirror the C ABI: site count, bonds, sublattice count (sites
     must be numbered sublattice by sublattice), group permutations and
-    flips, the irrep's characters, and the number of up spins.
+    flips, the irrep's characters, and the number of up spins.  `tuning` is
+    an optional dict with the fields of ed_tuning_t (all 0 = automatic):
+    index_mode, limits_bits, block_threads, blocks_per_cu, chunk_bits,
+    hash_load_pct, table_entry_bytes, search_mode (1 one-stage, 2 two-stage
+    representative search) and lanczos_direct (1 = no graph replay).
     """
 
     def __init__(self, n_sites, bonds, n_sublat, perm, flip, chi, n_up, tuning=None):
@@ -126,7 +130,10 @@ class MultiBasis:
 
     Batched vectors are complex128 tensors of shape [dim, K] (sector index
     fastest); column k restricted to the rows of sector k is that sector's
-    vector in the order of its own basis.
+    vector in the order of its own basis.  `tuning` takes the fields of
+    ed_tuning_t that apply to the shared basis and the batched kernel,
+    notably lanes_per_row (1, 2 or 4 lanes per row; 0 = automatic) and
+    search_mode.
     """
 
     def __init__(self, n_sites, bonds, n_sublat, perm, flip, chis, n_up, tuning=None):
