@@ -50,6 +50,19 @@ MEASURED_TRAFFIC = {
 }
 
 
+# Integer-op rate of the representative search, from the SQ_INSTS_VALU_INT32 /
+# _INT64 counters of the same profile (wave instructions x 64 lanes / kernel
+# time); not measured by this script.
+MEASURED_INT_OPS = {
+    ("square40_j1j2", 4, "hash-slot", 5): {
+        "rate": 9.3e12, "unit": "lane-ops/s", "valu_issue_floor_frac": 0.57,
+        "source": "profiles/k_apply_square40_j1j2_ns4.md (rocprofv3 --pmc SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64), "
+                  "not measured in this run"},
+}
+PROFILE_SOURCE = ("profiles/k_apply_square40_j1j2_ns4.md (rocprofv3 --pmc FETCH_SIZE, WRITE_SIZE, scaled by a "
+                  "plain copy), not measured in this run")
+
+
 def kernel_digest():
     import hashlib
     h = hashlib.sha256()
@@ -95,29 +108,13 @@ def _workload(name, n_sub):
 
 
 def _allk_workloads(n_sub, which="all"):
-    """Momentum sectors of the 36-site triangular cluster with translations
-    only: all 36, or the 20 inequivalent ones (Gamma, the three M points and
-    one momentum of every +-k pair; for real H the sector -k is the complex
-    conjugate of sector k)."""
-    from ed_inputs import lattice as lat
     from ed_inputs import workloads as wl
-    w0 = wl.triangular_36_momentum(0, n_sub=n_sub or 4)
-    ks = range(w0.cluster.n_elems)
-    if which == "inequivalent":
-        ks = [k for k in ks if k <= lat.conjugate_momentum_index(w0.cluster, k)]
-    return [wl.triangular_36_momentum(k, n_sub=n_sub or 4) for k in ks]
+    return wl.triangular_36_all_momenta(n_sub or 4, which)
 
 
 def _gamma_workloads(n_sub):
-    """The eight one-dimensional irreps at Gamma of the 36-site triangular
-    cluster's full group 36 T x C6v x spin flip: A1, A2, B1, B2 of C6v, each
-    with even and odd spin-flip parity."""
-    from ed_inputs import lattice as lat
     from ed_inputs import workloads as wl
-    w0 = wl.triangular_36(n_sub=n_sub or 4)
-    c = w0.cluster
-    return [wl.Workload(f"triangular36_G{p}{'e' if f > 0 else 'o'}", c, lat.characters(c, 0, pc, f), w0.n_up, w0.J)
-            for p, pc in enumerate(lat.point_group_chars_1d(c.point_group)) for f in (1, -1)]
+    return wl.triangular_36_gamma(n_sub or 4)
 
 
 BATCHED_WORKLOADS = {
@@ -266,6 +263,147 @@ def bench_allk(args):
     print(json.dumps(out))
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_square16(steps=200):
+    """The oracle on the 16-site square (4x4, k = 0, D = 822): basis, one full
+    H.v and a 200-step Lanczos, timed on the host cores."""
+    from ed_inputs import vectors as vec
+    from ed_inputs import workloads as wl
+    from oracle import bruteforce as bf
+    from oracle import lanczos as olz
+    w = wl.square_4x4()
+    m = bf.Model.from_workload(w)
+    t0 = time.perf_counter()
+    st, stab = bf.basis(m, w.n_up)
+    t_basis = time.perf_counter() - t0
+    x = vec.normal_vector(len(st))
+    t0 = time.perf_counter()
+    _, kept, _ = bf.apply(m, st, stab, x)
+    t_hv = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = olz.lanczos(lambda v: bf.apply(m, st, stab, v)[0], x, steps)
+    t_lz = time.perf_counter() - t0
+    return {"workload": "square16 (4x4, 16 T, k=0, Sz=0)", "dim": int(len(st)), "terms_per_hv": int(len(st) + kept),
+            "basis_s": t_basis, "hv_s": t_hv, "lanczos_steps": int(res["n_done"]), "lanczos_s": t_lz,
+            "e0": float(res["eigenvalues"][0]), "cores": int(bf.lib().orc_max_threads()), "kind": "oracle"}
+
+
+def time_adjoint(basis, J, x, reps, hv_ms):
+    """gx = H gy plus the per-bond sums, and the per-bond sums alone (both
+    synchronise, so wall time on the host is the device time)."""
+    import torch
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(vec_seed_target())
+    gy = torch.randn(basis.dim, dtype=basis.dtype, device="cuda", generator=gen)
+    basis.backward(J, x, gy)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        basis.backward(J, x, gy)          # gx = H gy and gJ_b (synchronises)
+    full_ms = (time.perf_counter() - t0) * 1e3 / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        basis.backward(J, x, gy, want_gx=False)
+    gj_ms = (time.perf_counter() - t0) * 1e3 / reps
+    print(f"[bench] adjoint {full_ms:.2f} ms (per-bond sums {gj_ms:.2f} ms, H.v {hv_ms:.2f} ms)", file=sys.stderr,
+          flush=True)
+    return {"backward_ms": full_ms, "per_bond_sums_ms": gj_ms, "hv_ms": hv_ms, "backward_over_hv": full_ms / hv_ms,
+            "n_bonds": int(basis.n_bonds)}
+
+
+def vec_seed_target():
+    from ed_inputs import vectors as vec
+    return vec.SEED_TARGET
+
+
+def bench_adjoint_c5(reps):
+    """Adjoint on the 32-site disorder workload (orbit-averaged couplings,
+    translation sector k = 0): backward time against one H.v."""
+    import torch
+    from paper_1804_05028_amd import ed
+    w, desc = _workload("square32_disorder", 0)
+    b = ed.Basis.from_workload(w)
+    try:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(0)
+        x = torch.randn(b.dim, dtype=b.dtype, device="cuda", generator=gen)
+        y = b.empty()
+        b.apply(w.J, x, out=y)
+        _, pack_ms, kernel_ms = b.apply_timed(w.J, x, out=y, reps=reps)
+        out = time_adjoint(b, w.J, x, reps, pack_ms + kernel_ms)
+        out.update(workload="square32_disorder", description=desc, dim=int(b.dim))
+        return out
+    finally:
+        b.close()
+        torch.cuda.empty_cache()
+
+
+def bench_gamma_batched(reps):
+    """The eight Gamma irreps of the 36-site triangular full group: one
+    batched H.v over shared representatives against one launch per sector."""
+    import torch
+    from paper_1804_05028_amd import ed
+    ws = _gamma_workloads(4)
+    J = ws[0].J
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    per_ms, per = 0.0, []
+    for w in ws:
+        b = ed.Basis.from_workload(w)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(0)
+        x = torch.randn(b.dim, dtype=b.dtype, device="cuda", generator=gen)
+        y = b.empty()
+        b.apply(J, x, out=y)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            b.apply(J, x, out=y)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        per.append(round(ms, 3))
+        per_ms += ms
+        del x, y
+        b.close()
+    mb = ed.MultiBasis.from_workloads(ws)
+    try:
+        info = mb.info()
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(0)
+        x = torch.randn((mb.dim, mb.K), dtype=torch.complex128, device="cuda", generator=gen)
+        y = mb.empty()
+        mb.apply(J, x, out=y)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            mb.apply(J, x, out=y)
+        ev1.record()
+        torch.cuda.synchronize()
+        bat_ms = ev0.elapsed_time(ev1) / reps
+        t, shared = mb.stats()
+        del x, y
+    finally:
+        mb.close()
+        torch.cuda.empty_cache()
+    print(f"[bench] Gamma irreps: per-sector {per_ms:.1f} ms, batched {bat_ms:.1f} ms ({per_ms / bat_ms:.2f}x)",
+          file=sys.stderr, flush=True)
+    return {"workload": "triangular36_gamma", "description": "36 T x C6v x flip, the 8 one-dimensional irreps at "
+                                                              "Gamma, Sz=0", "n_sectors": len(ws),
+            "per_sector_ms": per, "per_sector_total_ms": per_ms, "batched_ms": bat_ms, "speedup": per_ms / bat_ms,
+            "terms_per_hv": int(t.sum()), "shared_terms_per_hv": int(shared), "lanes_per_row": info["lanes_per_row"],
+            "chi_in_lds": info["chi_in_lds"], "timing": f"torch.cuda events on the launch stream, mean of {reps}"}
+
+
 def cpu_baseline(w, rows, seed):
     """Oracle (brute-force C) on a bounded sample of rows of the same H.v."""
     from ed_inputs import vectors as vec
@@ -276,7 +414,7 @@ def cpu_baseline(w, rows, seed):
     _, kept, _, _ = bf.rows_apply(m, sample, lambda s: vec.hashed_amplitudes(s, salt=1, complex_=w.is_complex))
     dt = time.perf_counter() - t0
     return dict(value=(kept + len(sample)) / dt, unit="terms/s", cores=int(bf.lib().orc_max_threads()),
-                kind="oracle",
+                kind="oracle", cpu_model=cpu_model(),
                 sample=f"{len(sample)} seeded random representatives (seed {seed}), all their H.v terms "
                        f"({kept + len(sample)} terms) by brute-force group application, {dt:.1f} s")
 
@@ -307,6 +445,8 @@ def main():
                     help="triangular36_allk: all 36 momenta, or the 20 inequivalent ones")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the adjoint (dL/dx = H gy and the per-bond sums) on the same basis")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: skip the batched Gamma-irrep, adjoint and small-oracle measurements")
     ap.add_argument("--autotune", action="store_true",
                     help="search sublattice decompositions and launch tunings first, then bench the fastest")
     args = ap.parse_args()
@@ -357,18 +497,15 @@ def main():
     x /= torch.linalg.norm(x)
     J = w.J
 
-    # ---- H.v kernel timing (HIP events on the launch stream) -----------------
+    # ---- H.v kernel timing: HIP events recorded by the library on the launch
+    # stream around the scatter of x into the index and around the kernel ------
     y = basis.empty()
     basis.apply(J, x, out=y)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.hv_reps):
-        basis.apply(J, x, out=y)
-    ev1.record()
-    torch.cuda.synchronize()
-    hv_ms = ev0.elapsed_time(ev1) / args.hv_reps
-    print(f"[bench] H.v kernel {hv_ms:.2f} ms  ({terms / hv_ms * 1e3:.3e} terms/s)", file=sys.stderr, flush=True)
+    _, pack_ms, kernel_ms = basis.apply_timed(J, x, out=y, reps=args.hv_reps)
+    hv_ms = pack_ms + kernel_ms
+    print(f"[bench] H.v kernel {kernel_ms:.2f} ms + scatter {pack_ms:.2f} ms  ({terms / hv_ms * 1e3:.3e} terms/s)",
+          file=sys.stderr, flush=True)
     if args.profile_only:
         # calibration for the HBM byte counters: one plain copy of D values
         torch.cuda.synchronize()
@@ -379,19 +516,7 @@ def main():
 
     adjoint = None
     if args.adjoint:
-        gy = torch.randn(D, dtype=dt, device="cuda", generator=gen)
-        basis.backward(J, x, gy)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.hv_reps):
-            basis.backward(J, x, gy)          # gx = H gy and gJ_b (synchronises)
-        full_ms = (time.perf_counter() - t0) * 1e3 / args.hv_reps
-        t0 = time.perf_counter()
-        for _ in range(args.hv_reps):
-            basis.backward(J, x, gy, want_gx=False)
-        gj_ms = (time.perf_counter() - t0) * 1e3 / args.hv_reps
-        adjoint = {"backward_ms": full_ms, "per_bond_sums_ms": gj_ms, "n_bonds": int(basis.n_bonds)}
-        print(f"[bench] adjoint {full_ms:.2f} ms (per-bond sums {gj_ms:.2f} ms)", file=sys.stderr, flush=True)
+        adjoint = time_adjoint(basis, J, x, args.hv_reps, hv_ms)
 
     # ---- Lanczos steps ----------------------------------------------------------
     if args.warmup > 0:
@@ -402,25 +527,44 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     steps_done = int(res["n_done"])
+    e0_after = float(res["eigenvalues"][0]) if len(res["eigenvalues"]) else None
     ms_per_step = elapsed * 1e3 / max(steps_done, 1)
     value = terms * steps_done / elapsed
 
     cplx = basis.is_complex
     br, bt = (BYTES_ROW_CPLX, BYTES_TERM_CPLX) if cplx else (BYTES_ROW_REAL, BYTES_TERM_REAL)
     alg_bytes = D * br + kept * bt
-    achieved = alg_bytes / (hv_ms * 1e-3) / 1e9
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     index_name = ["hash-slot", "limits"][info["index_mode"]]
-    traffic = measured_traffic((args.workload, info["n_sublat"], index_name, info["chunk_bits"]))
+    key = (args.workload, info["n_sublat"], index_name, info["chunk_bits"])
+    traffic = measured_traffic(key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "traffic_gbs": round(traffic / (hv_ms * 1e-3) / 1e9, 1) if traffic else None,
+                "traffic_source": PROFILE_SOURCE if traffic else None,
+                "traffic_gbs": round(traffic / (kernel_ms * 1e-3) / 1e9, 1) if traffic else None,
+                "lines_per_term": round(traffic / 128.0 / kept, 3) if traffic and kept else None,
                 "kernel": "k_apply (fused H.v)", "alg_bytes_per_launch": alg_bytes,
-                "launch_ms": round(hv_ms, 3)}
+                "alg_bytes_per_unit": {"row": br, "kept_term": bt},
+                "launch_ms": round(kernel_ms, 3), "scatter_ms": round(pack_ms, 3),
+                "timing": "HIP events recorded on the launch stream around the k_apply kernel, mean of "
+                          f"{args.hv_reps} launches"}
+
+    int_ops = MEASURED_INT_OPS.get(key) if traffic else None
+    del x, y, res
+    basis.close()
+    torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] CPU oracle baseline on {args.cpu_rows} rows", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, args.cpu_rows, 2)
+
+    extras = {}
+    if args.workload == "square40_j1j2" and not args.no_extras:
+        extras["batched"] = bench_gamma_batched(args.hv_reps)
+        extras["adjoint"] = bench_adjoint_c5(args.hv_reps)
+        if not args.no_cpu_baseline:
+            extras["oracle_square16"] = oracle_square16()
 
     out = {
         "metric": METRIC,
@@ -442,14 +586,17 @@ def main():
                    "chunk_bits": info["chunk_bits"], "lds_bytes": info["lds_bytes"], "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "int_ops": int_ops,
         "hv_terms_per_s": terms / (hv_ms * 1e-3),
+        "hv_ms": round(hv_ms, 3),
         "basis_build_s": build_s,
-        "lanczos_e0_after_steps": float(res["eigenvalues"][0]) if len(res["eigenvalues"]) else None,
+        "lanczos_e0_after_steps": e0_after,
     }
     if tuned is not None:
         out["autotune"] = tuned
     if adjoint is not None:
         out["adjoint"] = adjoint
+    out.update(extras)
     print(json.dumps(out))
 
 

@@ -131,6 +131,33 @@ def triangular_12(n_sub=3, spin_flip=True, momentum_index=0, rotations=True, mir
                     "Heisenberg, 12-site triangular")
 
 
+def triangular_36_all_momenta(n_sub=4, which="all"):
+    """Momentum sectors of the 36-site triangular cluster with translations
+    only: all 36, or the 20 inequivalent ones (Gamma, the three M points and
+    one momentum of every +-k pair; for real H the sector -k is the complex
+    conjugate of sector k)."""
+    w0 = triangular_36_momentum(0, n_sub=n_sub)
+    ks = range(w0.cluster.n_elems)
+    if which == "inequivalent":
+        ks = [k for k in ks if k <= lat.conjugate_momentum_index(w0.cluster, k)]
+    return [triangular_36_momentum(k, n_sub=n_sub) for k in ks]
+
+
+def gamma_irreps(w0):
+    """The one-dimensional irreps at Gamma of a cluster's full group: every
+    1-D point-group irrep, each with even and odd spin-flip parity."""
+    c = w0.cluster
+    return [Workload(f"{w0.name}_G{p}{'e' if f > 0 else 'o'}", c, lat.characters(c, 0, pc, f), w0.n_up, w0.J)
+            for p, pc in enumerate(lat.point_group_chars_1d(c.point_group)) for f in (1, -1)]
+
+
+def triangular_36_gamma(n_sub=4):
+    """The eight one-dimensional irreps at Gamma of the 36-site triangular
+    cluster's full group 36 T x C6v x spin flip: A1, A2, B1, B2 of C6v, each
+    with even and odd spin-flip parity."""
+    return gamma_irreps(triangular_36(n_sub=n_sub))
+
+
 WORKLOADS = {
     "square16": square_4x4,
     "triangular36": triangular_36,

@@ -233,6 +233,16 @@ int ed_basis_copy_norms(const ed_basis_t *b, uint16_t *host_out, void *stream);
 int ed_apply_H(const ed_basis_t *b, const double *J, const void *x_dev, void *y_dev, void *stream);
 
 /*
+ * Device timing of ed_apply_H: reps (1..1000) launches of y = H x on stream,
+ * with HIP events recorded on that stream around each launch's scatter of x
+ * into the hash-slot index and around its H.v kernel.  *pack_ms and
+ * *kernel_ms receive the mean duration of each per launch (the scatter is 0
+ * for the Limits index).  J, x, y as for ed_apply_H.  Synchronises.
+ */
+int ed_apply_H_timed(const ed_basis_t *b, const double *J, const void *x_dev, void *y_dev, int32_t reps,
+                     double *pack_ms, double *kernel_ms, void *stream);
+
+/*
  * XXZ form of ed_apply_H: each bond contributes the exchange
  * (Jxy_b / 2)(S+_p S-_q + S-_p S+_q) and the Ising term Jz_b Sz_p Sz_q, both
  * non-branching two-site terms (sec. "Parallel matrix-vector multiply"; the
@@ -303,6 +313,8 @@ typedef struct {
     int64_t device_bytes;
     double build_ms;
     int32_t lanes_per_row;      /* lanes per row of the batched H.v kernel     */
+    int32_t chi_in_lds;         /* 1: the character table is staged in LDS (counted in lds_bytes);
+                                   0: the kernel reads it from HBM through the caches            */
 } ed_multi_info_t;
 
 #define ED_LANCZOS_NO_GRAPH 1   /* ed_lanczos_batched: launch the step kernels directly */

@@ -31,7 +31,7 @@ def build(force=False):
     """Compile orc.c with gcc (OpenMP) into oracle/liborc.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
                                "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
@@ -52,6 +52,10 @@ def lib():
         L.orc_rep_many.restype = None
         L.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P, i64]
         L.orc_basis.restype = i64
+        L.orc_basis_range.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, u64, u64, P, P, i64]
+        L.orc_basis_range.restype = i64
+        L.orc_unrank.argtypes = [ctypes.c_int, ctypes.c_int, u64]
+        L.orc_unrank.restype = u64
         L.orc_apply.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, i64, P, P,
                                 P, P, ctypes.c_int, P, P]
         L.orc_apply.restype = None
@@ -134,6 +138,24 @@ def basis(model, n_up, count_only=False):
                      _p(states), _p(stab), d)
     assert d2 == d
     return states, stab
+
+
+def basis_range(model, n_up, rank_lo, rank_hi):
+    """Sector representatives (and stabiliser sizes) among the configurations
+    of ranks [rank_lo, rank_hi) in the ascending popcount-n_up enumeration."""
+    L = lib()
+    args = (model.n, n_up, model.ng, _p(model.perm), _p(model.flip), _p(model.chi), int(rank_lo), int(rank_hi))
+    d = L.orc_basis_range(*args, None, None, 0)
+    states = np.empty(d, np.uint64)
+    stab = np.empty(d, np.int32)
+    d2 = L.orc_basis_range(*args, _p(states), _p(stab), d)
+    assert d2 == d
+    return states, stab
+
+
+def unrank(n, n_up, r):
+    """The r-th (0-based) n-bit configuration with n_up set bits, ascending."""
+    return int(lib().orc_unrank(int(n), int(n_up), int(r)))
 
 
 def apply(model, states, stab, x, nthreads=None):

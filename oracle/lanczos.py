@@ -12,7 +12,10 @@ a dense symmetric eigensolver (numpy.linalg.eigh on T), which stays robust
 when many Ritz values nearly coincide (ghost copies after loss of
 orthogonality), where LAPACK's MRRR tridiagonal driver can fail.
 
-Pins: closed-form ground energies and the dense spectrum at small N.
+Pins: closed-form ground energies and the dense spectrum at small N
+(tests/test_oracle.py); the Ritz residual rule against a closed-form
+2x2 tridiagonal and against residuals ||H y - theta y|| formed from the
+Lanczos vectors themselves (tests/test_oracle_lanczos.py).
 """
 from __future__ import annotations
 
@@ -64,22 +67,22 @@ def tridiag_eigenvalues(alpha, beta):
     return np.linalg.eigvalsh(_tmatrix(alpha, beta))
 
 
-def ground_state(matvec, v0, n_steps):
-    """Lowest Ritz value and vector, by a second pass of the same recurrence."""
-    res = lanczos(matvec, v0, n_steps, want_vectors=True)
-    m = res["n_done"]
-    if m == 1:
-        return res["alpha"][0], res["vectors"][0]
-    w, s = np.linalg.eigh(_tmatrix(res["alpha"], res["beta"]))
-    psi = sum(s[k, 0] * res["vectors"][k] for k in range(m))
-    return w[0], psi / np.linalg.norm(psi)
+def ritz_residuals(alpha, beta):
+    """Ritz values of the m-step T and their residual norms.
+
+    For a Ritz pair (theta, y = V s) of m Lanczos steps, H y - theta y =
+    beta_m (e_m . s) v_{m+1}, so the residual norm is beta_m |s_m|, with s_m
+    the last component of the unit eigenvector s of T and beta_m the last
+    beta the recurrence produced.
+    """
+    m = len(alpha)
+    if m == 0:
+        return np.array([]), np.array([])
+    w, s = np.linalg.eigh(_tmatrix(alpha, beta))
+    return w, abs(beta[m - 1]) * np.abs(s[m - 1, :])
 
 
 def converged_ritz(alpha, beta, resid_tol=1e-8):
-    """Ritz values whose residual beta_m |s_m| is below resid_tol."""
-    m = len(alpha)
-    if m == 1:
-        return np.array([alpha[0]])
-    w, s = np.linalg.eigh(_tmatrix(alpha, beta))
-    res = abs(beta[m - 1]) * np.abs(s[m - 1, :])
+    """Ritz values whose residual beta_m |s_m| is below resid_tol, ascending."""
+    w, res = ritz_residuals(alpha, beta)
     return w[res < resid_tol]

@@ -46,7 +46,7 @@ uint64_t orc_act(int n, const int32_t *perm, int flip, uint64_t s)
 {
     uint64_t r = 0;
     for (int i = 0; i < n; ++i)
-        if (get_bit(s, n, i)) r |= 1ull << (n - 1 - perm[i]);
+        r |= (uint64_t)get_bit(s, n, i) << (n - 1 - perm[i]);
     if (flip) r ^= full_mask(n);
     return r;
 }
@@ -131,19 +131,27 @@ static uint64_t next_comb(uint64_t v)
     return (t + 1) | (((~t & -~t) - 1) >> (__builtin_ctzll(v) + 1));
 }
 
+/* r-th (0-based) state of the ascending enumeration, for callers that split it */
+uint64_t orc_unrank(int n, int k, uint64_t r) { return unrank(n, k, r); }
+
 /*
- * Enumerate the sector basis: every popcount-n_up configuration that equals its
- * representative and is compatible with chi.  If states_out is NULL only the
- * count is returned.  Otherwise at most cap entries are written, in ascending
- * order, together with the stabiliser sizes.  Returns the dimension.
+ * Enumerate the sector basis restricted to ranks [rank_lo, rank_hi) of the
+ * ascending list of popcount-n_up configurations: every configuration there
+ * that equals its representative and is compatible with chi.  If states_out
+ * is NULL only the count is returned.  Otherwise at most cap entries are
+ * written, in ascending order, together with the stabiliser sizes.  Returns
+ * the number of sector states in the range.
  */
-int64_t orc_basis(int n, int n_up, int ng, const int32_t *perm, const uint8_t *flip,
-                  const double *chi, uint64_t *states_out, int32_t *stab_out, int64_t cap)
+int64_t orc_basis_range(int n, int n_up, int ng, const int32_t *perm, const uint8_t *flip,
+                        const double *chi, uint64_t rank_lo, uint64_t rank_hi,
+                        uint64_t *states_out, int32_t *stab_out, int64_t cap)
 {
     uint64_t total = binom_u(n, n_up);
-    if (total == 0) return 0;
+    if (rank_hi > total) rank_hi = total;
+    if (rank_lo >= rank_hi) return 0;
+    uint64_t span = rank_hi - rank_lo;
     int nchunk = 256;
-    if ((uint64_t)nchunk > total) nchunk = (int)total;
+    if ((uint64_t)nchunk > span) nchunk = (int)span;
     int64_t *counts = (int64_t *)calloc((size_t)nchunk + 1, sizeof(int64_t));
     uint64_t **lists = (uint64_t **)calloc((size_t)nchunk, sizeof(uint64_t *));
     int32_t **stabs = (int32_t **)calloc((size_t)nchunk, sizeof(int32_t *));
@@ -151,20 +159,28 @@ int64_t orc_basis(int n, int n_up, int ng, const int32_t *perm, const uint8_t *f
 
 #pragma omp parallel for schedule(dynamic, 1)
     for (int c = 0; c < nchunk; ++c) {
-        uint64_t lo = (uint64_t)((unsigned __int128)total * (unsigned)c / (unsigned)nchunk);
-        uint64_t hi = (uint64_t)((unsigned __int128)total * (unsigned)(c + 1) / (unsigned)nchunk);
+        uint64_t lo = rank_lo + (uint64_t)((unsigned __int128)span * (unsigned)c / (unsigned)nchunk);
+        uint64_t hi = rank_lo + (uint64_t)((unsigned __int128)span * (unsigned)(c + 1) / (unsigned)nchunk);
         int64_t capl = 0, cnt = 0;
         uint64_t *lst = NULL;
         int32_t *stb = NULL;
         uint64_t s = unrank(n, n_up, lo);
         for (uint64_t r = lo; r < hi; ++r) {
-            int is_rep = 1;
+            /* s is a representative iff no image is smaller; the images equal
+               to s form its stabiliser, whose characters decide compatibility */
+            int is_rep = 1, st = 0;
+            double re = 0.0, im = 0.0;
             for (int g = 0; g < ng; ++g) {
-                if (orc_act(n, perm + (size_t)g * n, flip[g], s) < s) { is_rep = 0; break; }
+                uint64_t t = orc_act(n, perm + (size_t)g * n, flip[g], s);
+                if (t < s) { is_rep = 0; break; }
+                if (t == s) {
+                    ++st;
+                    re += chi[2 * g];
+                    im += chi[2 * g + 1];
+                }
             }
             if (is_rep) {
-                int comp;
-                int st = stabiliser(n, ng, perm, flip, chi, s, &comp);
+                int comp = fabs(re - st) < 1e-9 && fabs(im) < 1e-9;
                 if (comp) {
                     if (want) {
                         if (cnt == capl) {
@@ -200,6 +216,13 @@ int64_t orc_basis(int n, int n_up, int ng, const int32_t *perm, const uint8_t *f
     free(lists);
     free(stabs);
     return dim;
+}
+
+/* The whole sector basis: orc_basis_range over every rank. */
+int64_t orc_basis(int n, int n_up, int ng, const int32_t *perm, const uint8_t *flip,
+                  const double *chi, uint64_t *states_out, int32_t *stab_out, int64_t cap)
+{
+    return orc_basis_range(n, n_up, ng, perm, flip, chi, 0, binom_u(n, n_up), states_out, stab_out, cap);
 }
 
 static int64_t find_state(int64_t dim, const uint64_t *basis, uint64_t s)

@@ -78,7 +78,7 @@ class ed_multi_info_t(ctypes.Structure):
                 ("n_bonds", ctypes.c_int32), ("chunk_bits", ctypes.c_int32),
                 ("table_entry_bytes", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("n_slots", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
-                ("lanes_per_row", ctypes.c_int32)]
+                ("lanes_per_row", ctypes.c_int32), ("chi_in_lds", ctypes.c_int32)]
 
 
 ED_LANCZOS_NO_GRAPH = 1
@@ -109,6 +109,7 @@ PROTOTYPES = {
     "ed_basis_copy_norms": (ctypes.c_int, [P, P, P]),
     "ed_apply_H": (ctypes.c_int, [P, P, P, P, P]),
     "ed_apply_H_stats": (ctypes.c_int, [P, P, P, P, P]),
+    "ed_apply_H_timed": (ctypes.c_int, [P, P, P, P, I32, P, P, P]),
     "ed_lanczos": (ctypes.c_int, [P, P, P, I32, P, P, P, P, P]),
     "ed_apply_H_backward": (ctypes.c_int, [P, P, P, P, P, P, P]),
     "ed_tridiag_eigh": (ctypes.c_int, [I32, P, P, P, P]),
@@ -313,6 +314,16 @@ def ed_lanczos_xxz(h, Jxy, Jz, v0_dev, n_steps, psi0_dev=None, stream=None):
                                ptr(psi0_dev), stream))
     n = nd.value
     return alpha[:n].copy(), beta[:n].copy(), n
+
+
+def ed_apply_H_timed(h, J, x_dev, y_dev, reps, stream=None):
+    """reps launches of y = H x; returns the mean (scatter ms, H.v kernel ms)."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    pack = ctypes.c_double()
+    kern = ctypes.c_double()
+    check(lib().ed_apply_H_timed(h, J.ctypes.data, ptr(x_dev), ptr(y_dev), int(reps), ctypes.byref(pack),
+                                 ctypes.byref(kern), stream))
+    return pack.value, kern.value
 
 
 def ed_apply_H_stats(h, stream=None):

@@ -306,6 +306,16 @@ int ed_apply_H(const ed_basis_t *b, const double *J, const void *x_dev, void *y_
     return ed_apply_H_xxz(b, J, nullptr, x_dev, y_dev, stream);
 }
 
+int ed_apply_H_timed(const ed_basis_t *b, const double *J, const void *x_dev, void *y_dev, int32_t reps,
+                     double *pack_ms, double *kernel_ms, void *stream)
+{
+    if (!b || !J || !pack_ms || !kernel_ms || (b->db.dim > 0 && (!x_dev || !y_dev)))
+        return set_error(ED_ERR_ARG, "null argument");
+    if (x_dev == y_dev && b->db.dim > 0) return set_error(ED_ERR_ARG, "x and y must be distinct");
+    if (reps < 1 || reps > 1000) return set_error(ED_ERR_ARG, "reps = %d (1..1000)", reps);
+    return ed::launch_apply_timed(b, J, x_dev, y_dev, reps, pack_ms, kernel_ms, stream);
+}
+
 int ed_apply_H_xxz(const ed_basis_t *b, const double *Jxy, const double *Jz, const void *x_dev, void *y_dev,
                    void *stream)
 {
@@ -461,7 +471,8 @@ int ed_multi_info(const ed_multi_t *mb, ed_multi_info_t *info)
     info->n_bonds = b->t.nb;
     info->chunk_bits = b->dm.chunk_bits;
     info->table_entry_bytes = b->dm.act_bytes;
-    info->lds_bytes = (int32_t)(mb->lds_chi_off + (uint32_t)b->t.ng * mb->K * 16);
+    info->lds_bytes = (int32_t)(mb->lds_chi_off + (mb->chi_in_lds ? (uint32_t)b->t.ng * mb->K * 16 : 0u));
+    info->chi_in_lds = mb->chi_in_lds ? 1 : 0;
     info->n_slots = b->n_slots;
     info->device_bytes = b->device_bytes;
     info->build_ms = mb->build_ms;

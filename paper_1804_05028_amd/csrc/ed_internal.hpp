@@ -166,6 +166,8 @@ int launch_basis_build(ed_basis *b, void *stream);
 int multi_lanes_per_row(const ed_multi *mb);
 int launch_apply(const ed_basis *b, const double *J, const double *Jz, const void *x, void *y, void *stream, int stats_mode,
                  unsigned long long *stats_dev);
+int launch_apply_timed(const ed_basis *b, const double *J, const void *x, void *y, int reps, double *pack_ms,
+                       double *kernel_ms, void *stream);
 int launch_backward_J(const ed_basis *b, const double *J, const void *x, const void *gy, double *gJ_host,
                       void *stream);
 int run_lanczos(const ed_basis *b, const double *J, const double *Jz, const void *v0, int n_steps, double *alpha, double *beta,

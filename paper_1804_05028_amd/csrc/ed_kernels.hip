@@ -1185,6 +1185,54 @@ int launch_apply(const ed_basis *b, const double *J, const double *Jz, const voi
     return apply_dispatch<0>(b, x, y, nullptr, nullptr, nullptr, nullptr, jsq, st);
 }
 
+// ed_apply_H repeated reps times, with HIP events on the stream around the
+// amplitude scatter and around the H.v kernel of every launch
+int launch_apply_timed(const ed_basis *b, const double *J, const void *x, void *y, int reps, double *pack_ms,
+                       double *kernel_ms, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    int rc = check_couplings(b, J);
+    if (rc) return rc;
+    double jsq = 0.0;
+    rc = upload_couplings(b, J, nullptr, st, &jsq);
+    if (rc) return rc;
+    *pack_ms = 0.0;
+    *kernel_ms = 0.0;
+    if (b->db.dim == 0) return ED_OK;
+    std::vector<hipEvent_t> ev((size_t)reps * 3, nullptr);
+    auto destroy = [&]() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            destroy();
+            return set_error(ED_ERR_HIP, "event creation failed");
+        }
+    for (int r = 0; r < reps && rc == ED_OK; ++r) {
+        if (hipEventRecord(ev[3 * r], st) != hipSuccess) rc = set_error(ED_ERR_HIP, "event record failed");
+        if (!rc) rc = pack_input(b, x, st);
+        if (!rc && hipEventRecord(ev[3 * r + 1], st) != hipSuccess) rc = set_error(ED_ERR_HIP, "event record failed");
+        if (!rc) rc = apply_dispatch<0>(b, x, y, nullptr, nullptr, nullptr, nullptr, jsq, st);
+        if (!rc && hipEventRecord(ev[3 * r + 2], st) != hipSuccess) rc = set_error(ED_ERR_HIP, "event record failed");
+    }
+    if (!rc && hipStreamSynchronize(st) != hipSuccess)
+        rc = set_error(ED_ERR_HIP, "timed H.v failed: %s", hipGetErrorString(hipGetLastError()));
+    for (int r = 0; r < reps && rc == ED_OK; ++r) {
+        float a = 0.f, k = 0.f;
+        if (hipEventElapsedTime(&a, ev[3 * r], ev[3 * r + 1]) != hipSuccess ||
+            hipEventElapsedTime(&k, ev[3 * r + 1], ev[3 * r + 2]) != hipSuccess)
+            rc = set_error(ED_ERR_HIP, "event timing failed");
+        *pack_ms += a;
+        *kernel_ms += k;
+    }
+    destroy();
+    if (rc) return rc;
+    *pack_ms /= reps;
+    *kernel_ms /= reps;
+    return ED_OK;
+}
+
 // ---- adjoint ---------------------------------------------------------------
 
 template <bool CPLX, typename AT, int INDEX, int NSC>

@@ -104,6 +104,14 @@ class Basis:
     def stats(self):
         return L.ed_apply_H_stats(self.handle, _stream())
 
+    def apply_timed(self, J, x, out=None, reps=5):
+        """reps launches of y = H x; returns (y, mean scatter ms, mean H.v kernel ms)."""
+        self._check_vec(x, "x")
+        y = self.empty() if out is None else out
+        self._check_vec(y, "out")
+        pack_ms, kernel_ms = L.ed_apply_H_timed(self.handle, np.asarray(J, np.float64), x, y, reps, _stream())
+        return y, pack_ms, kernel_ms
+
     def lanczos(self, J, v0, n_steps, want_psi0=False, Jz=None):
         self._check_vec(v0, "v0")
         psi = self.empty() if want_psi0 else None

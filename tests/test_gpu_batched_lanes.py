@@ -104,3 +104,55 @@ def test_lane_count_raised_for_character_tables_in_hbm():
         finally:
             mb.close()
     assert np.array_equal(ys[1], ys[0])
+
+
+def _tri12_gamma():
+    """The eight Gamma irreps of the 12-site triangular full group (12 T x C6v
+    x flip, 288 elements) with four 3-site sublattices: 36 KB of characters,
+    read from HBM, as in the 36-site triangular Gamma benchmark."""
+    c = lat.triangular((2, 2), (-2, 4), spin_flip=True, superlattice=wl.TRI_4, name="triangular12_4sub")
+    return wl.gamma_irreps(wl.Workload("tri12", c, lat.characters(c, 0), 6, np.ones(c.n_bonds)))
+
+
+# Cases that run the compile-time batched instances of the benchmarks: four
+# sublattices with two action-table chunks (NSC 34, the all-momentum launches)
+# and three chunks (NSC 35, the Gamma-irrep launch), 2-byte entries, the
+# two-stage search, 2 and 4 lanes per row.
+BENCH_INSTANCES = [
+    ("sq16_allk_nsc34", lambda: _sectors(16), {"chunk_bits": 2}, 2, True),
+    ("sq16_k4_nsc34", lambda: _sectors(4), {"chunk_bits": 2}, 2, True),
+    ("tri12_gamma_nsc35", _tri12_gamma, {"chunk_bits": 1}, 3, False),
+]
+
+
+@pytest.mark.parametrize("lanes", [2, 4])
+@pytest.mark.parametrize("name,make,tune,chunks,chi_lds", BENCH_INSTANCES, ids=[c[0] for c in BENCH_INSTANCES])
+def test_benchmark_instances_match_oracle(name, make, tune, chunks, chi_lds, lanes):
+    ed = _ed()
+    ws = make()
+    tuning = dict(tune, table_entry_bytes=2, search_mode=2, lanes_per_row=lanes)
+    print(f"[lanes] {name} lanes={lanes}", flush=True)
+    mb = ed.MultiBasis.from_workloads(ws, tuning)
+    try:
+        info = mb.info()
+        assert info["n_sublat"] == 4 and info["table_entry_bytes"] == 2
+        assert info["lanes_per_row"] == lanes and info["chi_in_lds"] == int(chi_lds)
+        m_bits = ws[0].cluster.n_sites // 4
+        assert -(-m_bits // info["chunk_bits"]) == chunks
+        x = _x(mb.dim, mb.K, 61)
+        y = mb.apply(ws[0].J, torch.as_tensor(x).cuda()).cpu().numpy()
+        masks = mb.masks()
+    finally:
+        mb.close()
+    for k, w in enumerate(ws):
+        sel = ((masks >> np.uint64(k)) & np.uint64(1)).astype(bool)
+        m = bf.Model.from_workload(w)
+        st, stab = bf.basis(m, w.n_up)
+        assert np.array_equal(np.nonzero(sel)[0].size, len(st)), k
+        if len(st) == 0:
+            assert np.all(y[:, k] == 0)
+            continue
+        ref, _, _ = bf.apply(m, st, stab, x[sel, k])
+        assert np.linalg.norm(y[sel, k] - ref) <= RTOL * np.linalg.norm(ref), (name, k)
+        assert np.abs(y[sel, k] - ref).max() <= 10 * RTOL * max(np.abs(ref).max(), 1e-300), (name, k)
+        assert np.all(y[~sel, k] == 0)

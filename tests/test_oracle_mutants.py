@@ -30,8 +30,8 @@ MUTANTS = {
                             "d += same ? 0.25 * J[b] : -0.25 * J[b];\n        }\n        yt"),
     "ignore_compatibility": ("                if (comp) {\n                    if (want)",
                              "                if (1) {\n                    if (want)"),
-    "action_inverse": ("if (get_bit(s, n, i)) r |= 1ull << (n - 1 - perm[i]);",
-                       "if (get_bit(s, n, perm[i])) r |= 1ull << (n - 1 - i);"),
+    "action_inverse": ("r |= (uint64_t)get_bit(s, n, i) << (n - 1 - perm[i]);",
+                       "r |= (uint64_t)get_bit(s, n, perm[i]) << (n - 1 - i);"),
 }
 
 
@@ -41,7 +41,7 @@ def _build_mutant(tmp_path, name):
     assert src.count(old) >= 1, f"mutation anchor for {name} not found"
     src = src.replace(old, new)
     if name == "lsb_site_order":
-        src = src.replace("r |= 1ull << (n - 1 - perm[i]);", "r |= 1ull << perm[i];")
+        src = src.replace("<< (n - 1 - perm[i]);", "<< perm[i];")
         src = src.replace("(1ull << (n - 1 - p)) ^ (1ull << (n - 1 - q))", "(1ull << p) ^ (1ull << q)")
     path = os.path.join(str(tmp_path), f"liborc_{name}.so")
     csrc = os.path.join(str(tmp_path), f"orc_{name}.c")
