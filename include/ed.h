@@ -290,6 +290,20 @@ int ed_apply_H_backward(const ed_basis_t *b, const double *J, const void *x_dev,
                         void *gx_dev, double *gJ_host, void *stream);
 
 /*
+ * ed_apply_H_backward without device allocation, for callers that cannot
+ * allocate device memory (serving or training loops and harnesses that
+ * forbid hipMalloc).  Same arguments, results and synchronisation as
+ * ed_apply_H_backward; the per-bond partial sums live in a static device
+ * array of 2^19 doubles (4 MiB, held by every GPU the library runs on until
+ * the process ends) instead of buffers allocated per call.  A launch whose
+ * partial sums (blocks x (n_bonds + 1) + n_bonds + 1 doubles) exceed it
+ * returns ED_ERR_UNSUPPORTED.  Every call on one GPU uses that GPU's array:
+ * calls that overlap on one GPU (other threads or streams) race.
+ */
+int ed_apply_H_backward_noalloc(const ed_basis_t *b, const double *J, const void *x_dev, const void *gy_dev,
+                                void *gx_dev, double *gJ_host, void *stream);
+
+/*
  * Batched sectors.  Several 1-D irreps chi_0 .. chi_{K-1} (K <= 32) of one
  * group share one set of representatives: the orbit minima of the group,
  * i.e. the trivial-irrep basis (the representatives are the same for every

@@ -112,6 +112,7 @@ PROTOTYPES = {
     "ed_apply_H_timed": (ctypes.c_int, [P, P, P, P, I32, P, P, P]),
     "ed_lanczos": (ctypes.c_int, [P, P, P, I32, P, P, P, P, P]),
     "ed_apply_H_backward": (ctypes.c_int, [P, P, P, P, P, P, P]),
+    "ed_apply_H_backward_noalloc": (ctypes.c_int, [P, P, P, P, P, P, P]),
     "ed_tridiag_eigh": (ctypes.c_int, [I32, P, P, P, P]),
     "ed_apply_H_xxz": (ctypes.c_int, [P, P, P, P, P, P]),
     "ed_lanczos_xxz": (ctypes.c_int, [P, P, P, P, I32, P, P, P, P, P]),
@@ -348,6 +349,15 @@ def ed_apply_H_backward(h, J, x_dev, gy_dev, gx_dev=None, want_gJ=True, stream=N
     gJ = np.zeros(J.shape[0], np.float64) if want_gJ else None
     check(lib().ed_apply_H_backward(h, J.ctypes.data, ptr(x_dev), ptr(gy_dev), ptr(gx_dev),
                                     gJ.ctypes.data if gJ is not None else None, stream))
+    return gJ
+
+
+def ed_apply_H_backward_noalloc(h, J, x_dev, gy_dev, gx_dev=None, want_gJ=True, stream=None):
+    """ed_apply_H_backward with its partial sums in the library's static device array."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    gJ = np.zeros(J.shape[0], np.float64) if want_gJ else None
+    check(lib().ed_apply_H_backward_noalloc(h, J.ctypes.data, ptr(x_dev), ptr(gy_dev), ptr(gx_dev),
+                                            gJ.ctypes.data if gJ is not None else None, stream))
     return gJ
 
 

@@ -359,8 +359,8 @@ int ed_lanczos_xxz(const ed_basis_t *b, const double *Jxy, const double *Jz, con
     return rc;
 }
 
-int ed_apply_H_backward(const ed_basis_t *b, const double *J, const void *x_dev, const void *gy_dev, void *gx_dev,
-                        double *gJ_host, void *stream)
+static int backward_common(const ed_basis_t *b, const double *J, const void *x_dev, const void *gy_dev, void *gx_dev,
+                           double *gJ_host, void *stream, bool static_scratch)
 {
     if (!b) return set_error(ED_ERR_ARG, "null basis");
     if (b->db.dim > 0 && !gy_dev) return set_error(ED_ERR_ARG, "null gy");
@@ -371,10 +371,22 @@ int ed_apply_H_backward(const ed_basis_t *b, const double *J, const void *x_dev,
     }
     if (gJ_host) {
         if (b->db.dim > 0 && !x_dev) return set_error(ED_ERR_ARG, "null x");
-        int rc = ed::launch_backward_J(b, J, x_dev, gy_dev, gJ_host, stream);
+        int rc = ed::launch_backward_J(b, J, x_dev, gy_dev, gJ_host, stream, static_scratch);
         if (rc) return rc;
     }
     return ED_OK;
+}
+
+int ed_apply_H_backward(const ed_basis_t *b, const double *J, const void *x_dev, const void *gy_dev, void *gx_dev,
+                        double *gJ_host, void *stream)
+{
+    return backward_common(b, J, x_dev, gy_dev, gx_dev, gJ_host, stream, false);
+}
+
+int ed_apply_H_backward_noalloc(const ed_basis_t *b, const double *J, const void *x_dev, const void *gy_dev,
+                                void *gx_dev, double *gJ_host, void *stream)
+{
+    return backward_common(b, J, x_dev, gy_dev, gx_dev, gJ_host, stream, true);
 }
 
 // Symmetric tridiagonal eigenproblem: eigenvalues by Sturm-sequence

@@ -168,8 +168,8 @@ int launch_apply(const ed_basis *b, const double *J, const double *Jz, const voi
                  unsigned long long *stats_dev);
 int launch_apply_timed(const ed_basis *b, const double *J, const void *x, void *y, int reps, double *pack_ms,
                        double *kernel_ms, void *stream);
-int launch_backward_J(const ed_basis *b, const double *J, const void *x, const void *gy, double *gJ_host,
-                      void *stream);
+int launch_backward_J(const ed_basis *b, const double *J, const void *x, const void *gy, double *gJ_host, void *stream,
+                      bool static_scratch);
 int run_lanczos(const ed_basis *b, const double *J, const double *Jz, const void *v0, int n_steps, double *alpha, double *beta,
                 int *n_done, void *psi0, void *stream);
 int check_couplings(const ed_basis *b, const double *J);

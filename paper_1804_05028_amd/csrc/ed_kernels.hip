@@ -16,6 +16,8 @@
 // All lookup tables are staged once per persistent block in LDS.
 #include "ed_device.hpp"
 
+#include <mutex>
+
 namespace ed {
 
 // ---------------------------------------------------------------------------
@@ -1235,8 +1237,41 @@ int launch_apply_timed(const ed_basis *b, const double *J, const void *x, void *
 
 // ---- adjoint ---------------------------------------------------------------
 
+// Scratch of the allocation-free adjoint entry point: the per-block partial
+// sums [grid][nb + 1] of the per-bond adjoint and their column sums [nb + 1].
+// Each device holds its own copy; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device (scratch_on_device).
+constexpr size_t kScratchDoubles = (size_t)1 << 19;   // 4 MiB per device
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[kMaxDevices];
+
+// device address of the current device's scratch array, resolved once per
+// device with that device current
+static int scratch_on_device(double **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(ED_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(ED_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return ED_OK;
+}
+
+// per-bond adjoint sums; the partial sums live in scratch_dev when it is
+// given (at most kScratchDoubles doubles), else in buffers allocated here
 template <bool CPLX, typename AT, int INDEX, int NSC>
-static int backward_impl(const ed_basis *b, const void *x, const void *gy, double *gJ_host, hipStream_t st)
+static int backward_impl(const ed_basis *b, const void *x, const void *gy, double *gJ_host, double *scratch_dev,
+                         hipStream_t st)
 {
     using T = typename Scalar<CPLX>::T;
     auto kern = k_backward_J<CPLX, AT, INDEX, NSC>;
@@ -1245,27 +1280,40 @@ static int backward_impl(const ed_basis *b, const void *x, const void *gy, doubl
     launch_cfg(b, kern, b->dm.lds_total, &grid, &threads);
     // the block reduction reuses the table area: [waves][nb + 1] doubles
     const size_t lds = std::max((size_t)b->dm.lds_total, (size_t)(threads / kWave) * (nb + 1) * 8);
+    const size_t n_part = (size_t)grid * (nb + 1);
     double *partials = nullptr, *out = nullptr;
-    if (hipMalloc((void **)&partials, (size_t)grid * (nb + 1) * 8) != hipSuccess ||
-        hipMalloc((void **)&out, (size_t)(nb + 1) * 8) != hipSuccess) {
+    if (scratch_dev) {
+        if (n_part + (size_t)(nb + 1) > kScratchDoubles)
+            return set_error(ED_ERR_UNSUPPORTED, "adjoint partials of %zu doubles exceed the %zu-double scratch array",
+                             n_part + (size_t)(nb + 1), kScratchDoubles);
+        partials = scratch_dev;
+        out = scratch_dev + n_part;
+    } else if (hipMalloc((void **)&partials, n_part * 8) != hipSuccess ||
+               hipMalloc((void **)&out, (size_t)(nb + 1) * 8) != hipSuccess) {
         (void)hipGetLastError();
         if (partials) (void)hipFree(partials);
         return set_error(ED_ERR_OOM, "adjoint partials");
     }
+    // every block writes its whole row of partials and every column sum is
+    // written, so nothing has to start at zero
     hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, b->dm, b->db, (const T *)x, (const T *)gy, partials);
     hipLaunchKernelGGL(k_sum_partials_cols, dim3((nb + 256) / 256), dim3(256), 0, st, (const double *)partials, grid,
                        nb + 1, out);
-    std::vector<double> h((size_t)nb + 1);
-    hipError_t e = hipMemcpyAsync(h.data(), out, (size_t)(nb + 1) * 8, hipMemcpyDeviceToHost, st);
+    double h[kMaxBondWords * 64 + 1];
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h, out, (size_t)(nb + 1) * 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(partials);
-    (void)hipFree(out);
+    if (!scratch_dev) {
+        (void)hipFree(partials);
+        (void)hipFree(out);
+    }
     if (e != hipSuccess) return set_error(ED_ERR_HIP, "adjoint failed: %s", hipGetErrorString(e));
     for (int k = 0; k < nb; ++k) gJ_host[k] = h[k] + 0.25 * h[nb];
     return ED_OK;
 }
 
-int launch_backward_J(const ed_basis *b, const double *J, const void *x, const void *gy, double *gJ_host, void *stream)
+int launch_backward_J(const ed_basis *b, const double *J, const void *x, const void *gy, double *gJ_host, void *stream,
+                      bool static_scratch)
 {
     hipStream_t st = (hipStream_t)stream;
     int rc = check_couplings(b, J);
@@ -1277,6 +1325,11 @@ int launch_backward_J(const ed_basis *b, const double *J, const void *x, const v
         for (int k = 0; k < b->t.nb; ++k) gJ_host[k] = 0.0;
         return ED_OK;
     }
+    double *scratch_dev = nullptr;
+    if (static_scratch) {
+        rc = scratch_on_device(&scratch_dev);
+        if (rc) return rc;
+    }
     rc = pack_input(b, x, st);
     if (rc) return rc;
     const bool c = b->dm.is_complex;
@@ -1284,7 +1337,8 @@ int launch_backward_J(const ed_basis *b, const double *J, const void *x, const v
     // four sublattices with one to three chunks: search loops fixed at compile time
     const int nsc = (ix == IDX_HASH && b->dm.ns == 4 && b->dm.n_chunks <= 3) ? 32 + b->dm.n_chunks : 0;
 #define ED_CASE(C, A, I, K) \
-    if (c == C && w == (int)sizeof(A) && ix == I && nsc == K) return backward_impl<C, A, I, K>(b, x, gy, gJ_host, st);
+    if (c == C && w == (int)sizeof(A) && ix == I && nsc == K) \
+        return backward_impl<C, A, I, K>(b, x, gy, gJ_host, scratch_dev, st);
 #define ED_CASES(C, A) \
     ED_CASE(C, A, IDX_HASH, 0) ED_CASE(C, A, IDX_HASH, 33) ED_CASE(C, A, IDX_HASH, 34) ED_CASE(C, A, IDX_HASH, 35) \
     ED_CASE(C, A, IDX_LIMITS, 0)
