@@ -104,6 +104,9 @@ def _workload(name, n_sub):
                 "Heisenberg triangular 36 (6,0)x(0,6), 36 T, momentum sector k=1 (complex), Sz=0")
     if name == "square16":
         return wl.square_4x4(n_sub=n_sub or 4), "Heisenberg square 16 (4x4), 16T, k=0, Sz=0"
+    if name == "triangular36_tV":
+        return (wl.triangular_36_tV(n_sub=n_sub or 4, V=1.0),
+                "spinless fermions t=1 V=1, triangular 36 (6,0)x(0,6), 18 particles, 36T x C6v, Gamma.A1")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -404,14 +407,31 @@ def bench_gamma_batched(reps):
             "chi_in_lds": info["chi_in_lds"], "timing": f"torch.cuda events on the launch stream, mean of {reps}"}
 
 
+def wl_mod():
+    from ed_inputs import workloads as wl
+    return wl
+
+
 def cpu_baseline(w, rows, seed):
     """Oracle (brute-force C) on a bounded sample of rows of the same H.v."""
+    import numpy as np
     from ed_inputs import vectors as vec
     from oracle import bruteforce as bf
-    m = bf.Model.from_workload(w)
-    sample = bf.random_representatives(m, w.n_up, rows, seed)
-    t0 = time.perf_counter()
-    _, kept, _, _ = bf.rows_apply(m, sample, lambda s: vec.hashed_amplitudes(s, salt=1, complex_=w.is_complex))
+    amp = lambda s: vec.hashed_amplitudes(s, salt=1, complex_=w.is_complex)  # noqa: E731
+    if isinstance(w, wl_mod().FermionWorkload):
+        c = w.cluster
+        m = bf.FermionModel(c.n_sites, c.perm, w.chi, c.bonds, w.t, w.V)
+        sample = bf.random_representatives(bf.Model(c.n_sites, c.perm, c.flip, np.ones(c.n_elems)), w.n_up,
+                                           2 * rows, seed)
+        _, _, _, _, comp = bf.frep_many(m, sample)
+        sample = sample[comp][:rows]
+        t0 = time.perf_counter()
+        _, kept, _, _ = bf.frows_apply(m, sample, amp)
+    else:
+        m = bf.Model.from_workload(w)
+        sample = bf.random_representatives(m, w.n_up, rows, seed)
+        t0 = time.perf_counter()
+        _, kept, _, _ = bf.rows_apply(m, sample, amp)
     dt = time.perf_counter() - t0
     return dict(value=(kept + len(sample)) / dt, unit="terms/s", cores=int(bf.lib().orc_max_threads()),
                 kind="oracle", cpu_model=cpu_model(),
@@ -480,7 +500,8 @@ def main():
                  "trials": [(r["n_sub"], r["tuning"], r.get("hv_ms"), r.get("error")) for r in results]}
     print(f"[bench] building basis: {desc}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    basis = ed.Basis.from_workload(w, tuning)
+    fermions = isinstance(w, wl_mod().FermionWorkload)
+    basis = (ed.FermionBasis if fermions else ed.Basis).from_workload(w, tuning)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     info = basis.info()
@@ -495,14 +516,17 @@ def main():
     dt = basis.dtype
     x = torch.randn(D, dtype=dt, device="cuda", generator=gen)
     x /= torch.linalg.norm(x)
-    J = w.J
+    J, Jz = (w.t, w.V) if fermions else (w.J, None)
 
     # ---- H.v kernel timing: HIP events recorded by the library on the launch
     # stream around the scatter of x into the index and around the kernel ------
     y = basis.empty()
-    basis.apply(J, x, out=y)
+    if fermions:
+        basis.apply(J, x, out=y, V=Jz)
+    else:
+        basis.apply(J, x, out=y)
     torch.cuda.synchronize()
-    _, pack_ms, kernel_ms = basis.apply_timed(J, x, out=y, reps=args.hv_reps)
+    _, pack_ms, kernel_ms = basis.apply_timed(J, x, out=y, reps=args.hv_reps, Jz=Jz)
     hv_ms = pack_ms + kernel_ms
     print(f"[bench] H.v kernel {kernel_ms:.2f} ms + scatter {pack_ms:.2f} ms  ({terms / hv_ms * 1e3:.3e} terms/s)",
           file=sys.stderr, flush=True)
@@ -520,10 +544,10 @@ def main():
 
     # ---- Lanczos steps ----------------------------------------------------------
     if args.warmup > 0:
-        basis.lanczos(J, x, args.warmup)
+        basis.lanczos(J, x, args.warmup, **({"V": Jz} if fermions else {}))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = basis.lanczos(J, x, args.steps)
+    res = basis.lanczos(J, x, args.steps, **({"V": Jz} if fermions else {}))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     steps_done = int(res["n_done"])

@@ -158,6 +158,72 @@ def triangular_36_gamma(n_sub=4):
     return gamma_irreps(triangular_36(n_sub=n_sub))
 
 
+@dataclass
+class FermionWorkload:
+    """Fermions in the occupation-number basis: orbitals are the cluster's
+    sites, n_part particles, H = sum_b [-t_b (c+_p c_q + h.c.) + V_b n_p n_q]."""
+    name: str
+    cluster: lat.Cluster
+    chi: np.ndarray          # complex128 [n_elems]
+    n_part: int
+    t: np.ndarray            # float64 [n_bonds]
+    V: np.ndarray            # float64 [n_bonds]
+    description: str = ""
+
+    @property
+    def n_up(self):
+        return self.n_part
+
+    @property
+    def is_complex(self):
+        return bool(np.any(np.abs(self.chi.imag) > 1e-14))
+
+
+def triangular_36_tV(n_sub=4, V=1.0, n_part=18, pg_irrep=0):
+    """Spinless fermions on the 36-site triangular cluster, t = 1 and
+    nearest-neighbour V, 36 T x C6 (216 elements; with the mirrors the
+    fermionic tables, whose 4-byte entries carry sign parities, exceed the
+    LDS), Gamma, 1-D point-group irrep pg_irrep (0 = trivial)."""
+    sup = {3: TRI_3, 4: TRI_4, 9: TRI_9}[n_sub]
+    cl = lat.triangular((6, 0), (0, 6), mirrors=False, superlattice=sup, name="triangular36f")
+    pc = lat.point_group_chars_1d(cl.point_group)[pg_irrep]
+    return FermionWorkload(f"triangular36_tV_G{pg_irrep}", cl, lat.characters(cl, 0, pc), n_part,
+                           np.ones(cl.n_bonds), np.full(cl.n_bonds, float(V)),
+                           f"spinless t-V (t=1, V={V}), 36-site triangular, {n_part} fermions, 36 T x C6, Gamma")
+
+
+def hubbard_ring(L, t=1.0, U=4.0, n_part=None, momentum_index=0, n_sub=2):
+    """L-site Hubbard ring as 2L orbitals (spin up 0..L-1, spin down
+    L..2L-1), translations acting on both species; hopping bonds within each
+    species and on-site bonds (i up, i down) with t = 0 and V = U.  The two
+    species form the sublattice blocks (n_sub = 2), or each species splits
+    into even and odd sites (n_sub = 4, L even)."""
+    n = 2 * L
+    if n_sub == 2:
+        order = list(range(n))
+    else:
+        order = [i for i in range(L) if i % 2 == 0] + [i for i in range(L) if i % 2 == 1]
+        order = order + [L + i for i in order]
+    pos = {o: k for k, o in enumerate(order)}          # orbital -> renumbered site
+    perm = np.zeros((L, n), np.int32)
+    for s in range(L):
+        for i in range(L):
+            perm[s, pos[i]] = pos[(i + s) % L]
+            perm[s, pos[L + i]] = pos[L + (i + s) % L]
+    hop = [(i, (i + 1) % L) for i in range(L)]
+    bonds = [(pos[p], pos[q]) for p, q in hop] + [(pos[L + p], pos[L + q]) for p, q in hop] + \
+            [(pos[i], pos[L + i]) for i in range(L)]
+    tt = np.array([t] * (2 * L) + [0.0] * L)
+    V = np.array([0.0] * (2 * L) + [U] * L)
+    chi = np.exp(2j * np.pi * momentum_index * np.arange(L) / L)
+    cl = lat.Cluster(name=f"hubbard{L}", n_sites=n, coords=list(range(n)), bonds=np.array(bonds, np.int32),
+                     bond_kind=np.zeros(len(bonds), np.int32), perm=perm, flip=np.zeros(L, np.uint8),
+                     trans=np.stack([np.arange(L), np.zeros(L, int)], 1).astype(np.int32),
+                     rot_index=np.zeros(L, np.int32), point_group=[((1, 0), (0, 1))], n_sublat=n_sub, periods=(L,))
+    return FermionWorkload(f"hubbard{L}_k{momentum_index}", cl, chi, L if n_part is None else n_part, tt, V,
+                           f"Hubbard ring L={L}, t={t}, U={U}")
+
+
 WORKLOADS = {
     "square16": square_4x4,
     "triangular36": triangular_36,

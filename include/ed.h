@@ -116,7 +116,8 @@ typedef struct {
                                running the row's searches and holding every lanes-th sector; 0 = 1 lane for K <= 2, 2 lanes for K <= 8, else 4.
                                When |G| K 16 bytes of characters exceed 32 KB they are read from
                                HBM, and the lane count is raised to at least 2 for K > 4 and 4
-                               for K > 16 (ed_multi_info reports the count used)                */
+                               for K > 16, and K > 32 always runs 4 lanes (ed_multi_info reports the
+                               count used)                                                          */
     int32_t lanczos_direct; /* ed_lanczos: 1 = launch each step's kernels directly; 0 = capture the
                                step once per buffer assignment in a HIP graph and replay it        */
 } ed_tuning_t;
@@ -152,6 +153,7 @@ typedef struct {
     int32_t search_mode;        /* search of the H.v kernels: ED_SEARCH_ONE_STAGE or _TWO_STAGE */
     double mean_candidates;     /* candidate symmetries per search, host Alg. 2 on 2048 random
                                    configurations at this n_up                  */
+    int32_t is_fermion;         /* built by ed_build_basis_fermions             */
 } ed_basis_info_t;
 
 /* Library version string (static). */
@@ -233,14 +235,15 @@ int ed_basis_copy_norms(const ed_basis_t *b, uint16_t *host_out, void *stream);
 int ed_apply_H(const ed_basis_t *b, const double *J, const void *x_dev, void *y_dev, void *stream);
 
 /*
- * Device timing of ed_apply_H: reps (1..1000) launches of y = H x on stream,
+ * Device timing of the H.v: reps (1..1000) launches of y = H x on stream,
  * with HIP events recorded on that stream around each launch's scatter of x
  * into the hash-slot index and around its H.v kernel.  *pack_ms and
  * *kernel_ms receive the mean duration of each per launch (the scatter is 0
- * for the Limits index).  J, x, y as for ed_apply_H.  Synchronises.
+ * for the Limits index).  Spin bases: J and Jz as for ed_apply_H_xxz;
+ * fermionic bases: t and V of ed_apply_H_fermions.  Synchronises.
  */
-int ed_apply_H_timed(const ed_basis_t *b, const double *J, const void *x_dev, void *y_dev, int32_t reps,
-                     double *pack_ms, double *kernel_ms, void *stream);
+int ed_apply_H_timed(const ed_basis_t *b, const double *J, const double *Jz, const void *x_dev, void *y_dev,
+                     int32_t reps, double *pack_ms, double *kernel_ms, void *stream);
 
 /*
  * XXZ form of ed_apply_H: each bond contributes the exchange
@@ -253,6 +256,44 @@ int ed_apply_H_timed(const ed_basis_t *b, const double *J, const void *x_dev, vo
  */
 int ed_apply_H_xxz(const ed_basis_t *b, const double *Jxy, const double *Jz, const void *x_dev, void *y_dev,
                    void *stream);
+
+/*
+ * Fermions in the occupation-number basis (sec. "Discussion": the sublattice
+ * coding carries over to fermionic Hamiltonians written in occupation
+ * numbers, with a Fermi sign besides the representative and its symmetry).
+ * The lattice's sites are orbitals, numbered as above (orbital i <-> bit
+ * N-1-i, sublattice blocks as for spins); a configuration stands for the
+ * ordered product c+_{i1} ... c+_{ik} |0>, i1 < ... < ik, of its occupied
+ * orbitals.  A group element (no spin flip) maps c+_i to c+_{perm[i]}: the
+ * image of a configuration is its permuted pattern times (-1) to the number
+ * of occupied pairs whose order it reverses.  The sector of the 1-D irrep
+ * chi holds the orbit minima whose symmetrised states survive, i.e. chi(g)
+ * equals that sign for every g of the stabiliser.  Spinful models take two
+ * orbitals per site (the group permuting both species alike).
+ *
+ * ed_build_basis_fermions: as ed_build_basis with n_particles occupied
+ * orbitals; ED_ERR_UNSUPPORTED for flip elements, the Limits index, 1- or
+ * 2-byte table entries, or blocks of more than 16 orbitals.
+ *
+ * ed_apply_H_fermions: y = H x for
+ *   H = sum_b [ -t_b (c+_p c_q + c+_q c_p) + V_b n_p n_q ],
+ * in gather form: y_i = sum_b V_b n_p n_q x_i + sum over bonds with one of
+ * p, q occupied of -t_b (-1)^(occupied orbitals strictly between p and q)
+ * (-1)^(Fermi sign of g on the hopped configuration) chi(g)
+ * sqrt(n_j / n_i) x_j, g mapping it to its representative sigma_j.  t and V:
+ * host [n_bonds], each constant on bond orbits; V may be NULL (0).  x, y as
+ * for ed_apply_H.  ed_apply_H, ed_apply_H_xxz and ed_lanczos(_xxz) reject
+ * fermionic bases with ED_ERR_ARG, and the fermionic calls reject spin
+ * bases; the adjoint and the batched calls cover spins only.
+ *
+ * ed_lanczos_fermions: ed_lanczos with the fermionic H.v.
+ */
+int ed_build_basis_fermions(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irrep_t *irrep,
+                            int32_t n_particles, const ed_tuning_t *tuning, void *stream, ed_basis_t **out);
+int ed_apply_H_fermions(const ed_basis_t *b, const double *t, const double *V, const void *x_dev, void *y_dev,
+                        void *stream);
+int ed_lanczos_fermions(const ed_basis_t *b, const double *t, const double *V, const void *v0_dev, int32_t n_steps,
+                        double *alpha_host, double *beta_host, int32_t *n_done, void *psi0_dev, void *stream);
 
 /*
  * Term counts of one H.v: diagonal terms (= dim), off-diagonal terms whose
@@ -304,7 +345,7 @@ int ed_apply_H_backward_noalloc(const ed_basis_t *b, const double *J, const void
                                 void *gx_dev, double *gJ_host, void *stream);
 
 /*
- * Batched sectors.  Several 1-D irreps chi_0 .. chi_{K-1} (K <= 32) of one
+ * Batched sectors.  Several 1-D irreps chi_0 .. chi_{K-1} (K <= 64) of one
  * group share one set of representatives: the orbit minima of the group,
  * i.e. the trivial-irrep basis (the representatives are the same for every
  * irrep, sec. "Symmetry adapted basis states"; an irrep keeps those whose
@@ -337,7 +378,11 @@ typedef struct {
  * Build the shared basis of n_sectors irreps (irreps[k].chi: host
  * [n_elems][2] each); validates every irrep as ed_validate does.  tuning may
  * be NULL; the index is always the hash-slot index and action-table entries
- * are 2 or 4 bytes wide.  Synchronises stream.
+ * are 2 or 4 bytes wide.  Up to 32 sectors the slot probe of a term returns
+ * the target's sector mask; from 33 to 64 sectors the mask is read from a
+ * per-row array, the H.v runs 4 lanes per row, and the character table
+ * (|G| K 16 bytes) must fit the 32 KB staged in LDS (else ED_ERR_UNSUPPORTED).
+ * Synchronises stream.
  */
 int ed_build_multi(const ed_lattice_t *lat, const ed_group_t *grp, int32_t n_sectors, const ed_irrep_t *irreps,
                    int32_t n_up, const ed_tuning_t *tuning, void *stream, ed_multi_t **out);

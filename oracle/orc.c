@@ -358,3 +358,212 @@ int orc_max_threads(void)
     return 1;
 #endif
 }
+
+/* ======================================================================
+ * Fermions in the occupation-number basis (sec. "Discussion": the method
+ * carries over to fermionic Hamiltonians written in occupation numbers,
+ * where a Fermi sign joins the representative and its symmetry).
+ *
+ * A configuration lists which orbitals are occupied, orbital i <-> bit
+ * N-1-i, and stands for the ordered product of creation operators
+ * c+_{i1} c+_{i2} ... c+_{ik} |0> with i1 < i2 < ... < ik.  A group element
+ * moves orbital i to perm[i]; as an operator it maps c+_i to c+_{perm[i]},
+ * so the image of a configuration is its permuted occupation pattern times
+ * the sign of the permutation that sorts (perm[i1], ..., perm[ik]), i.e.
+ * (-1)^(number of occupied pairs i < j with perm[i] > perm[j]).  Spin flip
+ * is not part of a fermionic group here.
+ *
+ * Hamiltonian: every bond b = (p, q) carries a hopping -t_b (c+_p c_q +
+ * c+_q c_p) and a density interaction V_b n_p n_q.  c+_p c_q on a
+ * configuration with q occupied and p empty gives the configuration with
+ * the two swapped, times (-1)^(occupied orbitals strictly between p and q).
+ * ====================================================================== */
+
+/* parity of the Fermi sign of the group element perm on configuration s */
+int orc_fsign(int n, const int32_t *perm, uint64_t s)
+{
+    int inv = 0;
+    for (int a = 0; a < n; ++a) {
+        if (!get_bit(s, n, a)) continue;
+        for (int b = a + 1; b < n; ++b)
+            if (get_bit(s, n, b) && perm[a] > perm[b]) ++inv;
+    }
+    return inv & 1;
+}
+
+/* parity of the number of occupied orbitals strictly between p and q */
+static int hop_parity(uint64_t s, int n, int p, int q)
+{
+    int lo = p < q ? p : q, hi = p < q ? q : p, c = 0;
+    for (int i = lo + 1; i < hi; ++i) c += get_bit(s, n, i);
+    return c & 1;
+}
+
+/* stabiliser size of s and whether chi(g) equals the Fermi sign of g on s for
+   every g of the stabiliser (otherwise the symmetrised state vanishes) */
+static int fstabiliser(int n, int ng, const int32_t *perm, const double *chi, uint64_t s, int *compatible)
+{
+    int cnt = 0;
+    double re = 0.0, im = 0.0;
+    for (int g = 0; g < ng; ++g) {
+        const int32_t *pg = perm + (size_t)g * n;
+        if (orc_act(n, pg, 0, s) == s) {
+            const double sg = orc_fsign(n, pg, s) ? -1.0 : 1.0;
+            ++cnt;
+            re += sg * chi[2 * g];
+            im += sg * chi[2 * g + 1];
+        }
+    }
+    *compatible = fabs(re - cnt) < 1e-9 && fabs(im) < 1e-9;
+    return cnt;
+}
+
+/* representative, first minimiser, stabiliser size and compatibility */
+void orc_frep_many(int n, int ng, const int32_t *perm, const double *chi, int64_t m, const uint64_t *in,
+                   uint64_t *rep_out, int32_t *g_out, int32_t *sign_out, int32_t *stab_out, uint8_t *compat_out)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < m; ++k) {
+        uint64_t best = ~0ull;
+        int32_t bg = -1;
+        for (int g = 0; g < ng; ++g) {
+            uint64_t t = orc_act(n, perm + (size_t)g * n, 0, in[k]);
+            if (t < best) { best = t; bg = g; }
+        }
+        int comp;
+        int st = fstabiliser(n, ng, perm, chi, best, &comp);
+        rep_out[k] = best;
+        if (g_out) g_out[k] = bg;
+        if (sign_out) sign_out[k] = orc_fsign(n, perm + (size_t)bg * n, in[k]);
+        if (stab_out) stab_out[k] = st;
+        if (compat_out) compat_out[k] = (uint8_t)comp;
+    }
+}
+
+/* sector basis of n_part fermions: the orbit minima whose symmetrised state
+   does not vanish, ascending, with their stabiliser sizes */
+int64_t orc_fbasis(int n, int n_part, int ng, const int32_t *perm, const double *chi, uint64_t *states_out,
+                   int32_t *stab_out, int64_t cap)
+{
+    uint64_t total = binom_u(n, n_part);
+    int64_t dim = 0;
+    if (total == 0) return 0;
+    uint64_t s = unrank(n, n_part, 0);
+    for (uint64_t r = 0; r < total; ++r) {
+        int is_rep = 1;
+        for (int g = 0; g < ng && is_rep; ++g)
+            if (orc_act(n, perm + (size_t)g * n, 0, s) < s) is_rep = 0;
+        if (is_rep) {
+            int comp;
+            int st = fstabiliser(n, ng, perm, chi, s, &comp);
+            if (comp) {
+                if (states_out && dim < cap) {
+                    states_out[dim] = s;
+                    stab_out[dim] = st;
+                }
+                ++dim;
+            }
+        }
+        if (r + 1 < total) s = next_comb(s);
+    }
+    return dim;
+}
+
+/*
+ * y = H x in the fermionic sector, scatter order: every source state sends
+ * each hop to its target representative sigma~' = h sigma' (h the first
+ * minimiser) with the element
+ *   -t_b (-1)^hop (-1)^fsign(h, sigma') conj(chi(h)) sqrt(n_i / n_j),
+ * the projection of the hopped configuration onto the target's symmetrised
+ * state; the diagonal is sum_b V_b n_p n_q.  x, y complex interleaved.
+ */
+void orc_fapply(int n, int ng, const int32_t *perm, const double *chi, int nb, const int32_t *bonds,
+                const double *t, const double *V, int64_t dim, const uint64_t *basis, const int32_t *stab,
+                const double *x, double *y, int64_t *kept, int64_t *dropped)
+{
+    int64_t k = 0, dd = 0;
+    memset(y, 0, sizeof(double) * (size_t)dim * 2);
+    for (int64_t j = 0; j < dim; ++j) {
+        uint64_t s = basis[j];
+        double xr = x[2 * j], xi = x[2 * j + 1];
+        double d = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            int p = bonds[2 * b], q = bonds[2 * b + 1];
+            if (get_bit(s, n, p) && get_bit(s, n, q)) d += V ? V[b] : 0.0;
+        }
+        y[2 * j] += d * xr;
+        y[2 * j + 1] += d * xi;
+        for (int b = 0; b < nb; ++b) {
+            int p = bonds[2 * b], q = bonds[2 * b + 1];
+            if (get_bit(s, n, p) == get_bit(s, n, q)) continue;
+            uint64_t sp = s ^ (1ull << (n - 1 - p)) ^ (1ull << (n - 1 - q));
+            uint64_t best = ~0ull;
+            int32_t h = -1;
+            for (int g = 0; g < ng; ++g) {
+                uint64_t tt = orc_act(n, perm + (size_t)g * n, 0, sp);
+                if (tt < best) { best = tt; h = g; }
+            }
+            int64_t i = find_state(dim, basis, best);
+            if (i < 0) { ++dd; continue; }
+            ++k;
+            int par = hop_parity(s, n, p, q) ^ orc_fsign(n, perm + (size_t)h * n, sp);
+            double amp = -t[b] * (par ? -1.0 : 1.0) * sqrt((double)stab[i] / (double)stab[j]);
+            double cr = amp * chi[2 * h], ci = -amp * chi[2 * h + 1]; /* conj(chi(h)) */
+            y[2 * i] += cr * xr - ci * xi;
+            y[2 * i + 1] += cr * xi + ci * xr;
+        }
+    }
+    if (kept) *kept = k;
+    if (dropped) *dropped = dd;
+}
+
+/*
+ * Rows of the Hermitian fermionic sector matrix for sampled representatives
+ * (the conjugate of what each row sends in orc_fapply): row stabiliser and
+ * compatibility, diagonal, and per bond the target representative, its
+ * stabiliser size, flag (0 no hop, 1 kept, 2 target not in the sector) and
+ * element -t_b (-1)^(hop + fsign) chi(h) sqrt(n_target / n_row).
+ */
+void orc_frow_terms(int n, int ng, const int32_t *perm, const double *chi, int nb, const int32_t *bonds,
+                    const double *t, const double *V, int64_t nrows, const uint64_t *rows, int32_t *row_stab,
+                    uint8_t *row_compat, double *row_diag, uint64_t *tgt, int32_t *tgt_stab, uint8_t *tgt_flag,
+                    double *coef)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t r = 0; r < nrows; ++r) {
+        uint64_t s = rows[r];
+        int comp;
+        int ns_ = fstabiliser(n, ng, perm, chi, s, &comp);
+        row_stab[r] = ns_;
+        row_compat[r] = (uint8_t)comp;
+        double d = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            int p = bonds[2 * b], q = bonds[2 * b + 1];
+            size_t o = (size_t)r * nb + b;
+            if (get_bit(s, n, p) && get_bit(s, n, q)) d += V ? V[b] : 0.0;
+            tgt[o] = 0;
+            tgt_stab[o] = 0;
+            tgt_flag[o] = 0;
+            coef[2 * o] = 0.0;
+            coef[2 * o + 1] = 0.0;
+            if (get_bit(s, n, p) == get_bit(s, n, q)) continue;
+            uint64_t sp = s ^ (1ull << (n - 1 - p)) ^ (1ull << (n - 1 - q));
+            uint64_t best = ~0ull;
+            int32_t h = -1;
+            for (int g = 0; g < ng; ++g) {
+                uint64_t tt = orc_act(n, perm + (size_t)g * n, 0, sp);
+                if (tt < best) { best = tt; h = g; }
+            }
+            int tc;
+            int nt = fstabiliser(n, ng, perm, chi, best, &tc);
+            tgt[o] = best;
+            tgt_stab[o] = nt;
+            tgt_flag[o] = tc ? 1 : 2;
+            int par = hop_parity(s, n, p, q) ^ orc_fsign(n, perm + (size_t)h * n, sp);
+            double amp = -t[b] * (par ? -1.0 : 1.0) * sqrt((double)nt / (double)ns_);
+            coef[2 * o] = amp * chi[2 * h];
+            coef[2 * o + 1] = amp * chi[2 * h + 1];
+        }
+        row_diag[r] = d;
+    }
+}

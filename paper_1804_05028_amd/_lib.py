@@ -69,7 +69,7 @@ class ed_basis_info_t(ctypes.Structure):
                 ("chunk_bits", ctypes.c_int32), ("table_entry_bytes", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double), ("search_mode", ctypes.c_int32),
-                ("mean_candidates", ctypes.c_double)]
+                ("mean_candidates", ctypes.c_double), ("is_fermion", ctypes.c_int32)]
 
 
 class ed_multi_info_t(ctypes.Structure):
@@ -109,7 +109,10 @@ PROTOTYPES = {
     "ed_basis_copy_norms": (ctypes.c_int, [P, P, P]),
     "ed_apply_H": (ctypes.c_int, [P, P, P, P, P]),
     "ed_apply_H_stats": (ctypes.c_int, [P, P, P, P, P]),
-    "ed_apply_H_timed": (ctypes.c_int, [P, P, P, P, I32, P, P, P]),
+    "ed_apply_H_timed": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P]),
+    "ed_build_basis_fermions": (ctypes.c_int, [P, P, P, I32, P, P, P]),
+    "ed_apply_H_fermions": (ctypes.c_int, [P, P, P, P, P, P]),
+    "ed_lanczos_fermions": (ctypes.c_int, [P, P, P, P, I32, P, P, P, P, P]),
     "ed_lanczos": (ctypes.c_int, [P, P, P, I32, P, P, P, P, P]),
     "ed_apply_H_backward": (ctypes.c_int, [P, P, P, P, P, P, P]),
     "ed_apply_H_backward_noalloc": (ctypes.c_int, [P, P, P, P, P, P, P]),
@@ -262,6 +265,15 @@ def ed_build_basis(arrays: ModelArrays, n_up, tuning=None, stream=None):
     return h
 
 
+def ed_build_basis_fermions(arrays: ModelArrays, n_particles, tuning=None, stream=None):
+    lat, grp, irr = arrays.refs()
+    h = ctypes.c_void_p()
+    tn = _tuning(tuning)
+    check(lib().ed_build_basis_fermions(lat, grp, irr, int(n_particles),
+                                        ctypes.byref(tn) if tn is not None else None, stream, ctypes.byref(h)))
+    return h
+
+
 def ed_free_basis(h):
     lib().ed_free_basis(h)
 
@@ -317,14 +329,34 @@ def ed_lanczos_xxz(h, Jxy, Jz, v0_dev, n_steps, psi0_dev=None, stream=None):
     return alpha[:n].copy(), beta[:n].copy(), n
 
 
-def ed_apply_H_timed(h, J, x_dev, y_dev, reps, stream=None):
+def ed_apply_H_timed(h, J, Jz, x_dev, y_dev, reps, stream=None):
     """reps launches of y = H x; returns the mean (scatter ms, H.v kernel ms)."""
     J = np.ascontiguousarray(J, dtype=np.float64)
+    Jz = None if Jz is None else np.ascontiguousarray(Jz, dtype=np.float64)
     pack = ctypes.c_double()
     kern = ctypes.c_double()
-    check(lib().ed_apply_H_timed(h, J.ctypes.data, ptr(x_dev), ptr(y_dev), int(reps), ctypes.byref(pack),
-                                 ctypes.byref(kern), stream))
+    check(lib().ed_apply_H_timed(h, J.ctypes.data, None if Jz is None else Jz.ctypes.data, ptr(x_dev), ptr(y_dev),
+                                 int(reps), ctypes.byref(pack), ctypes.byref(kern), stream))
     return pack.value, kern.value
+
+
+def ed_apply_H_fermions(h, t, V, x_dev, y_dev, stream=None):
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    V = None if V is None else np.ascontiguousarray(V, dtype=np.float64)
+    return check(lib().ed_apply_H_fermions(h, t.ctypes.data, None if V is None else V.ctypes.data, ptr(x_dev),
+                                           ptr(y_dev), stream))
+
+
+def ed_lanczos_fermions(h, t, V, v0_dev, n_steps, psi0_dev=None, stream=None):
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    V = None if V is None else np.ascontiguousarray(V, dtype=np.float64)
+    a = np.zeros(max(n_steps, 1), np.float64)
+    b = np.zeros(max(n_steps, 1), np.float64)
+    n = ctypes.c_int32(0)
+    check(lib().ed_lanczos_fermions(h, t.ctypes.data, None if V is None else V.ctypes.data, ptr(v0_dev),
+                                    int(n_steps), a.ctypes.data, b.ctypes.data, ctypes.byref(n), ptr(psi0_dev),
+                                    stream))
+    return a[: n.value].copy(), b[: n.value].copy(), n.value
 
 
 def ed_apply_H_stats(h, stream=None):

@@ -140,7 +140,8 @@ static double sample_mean_candidates(const ed::Tables &t, int n_up)
 static constexpr double kTwoStageMinCandidates = 3.0;
 
 static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irrep_t *irrep, int32_t n_up,
-                              const ed_tuning_t *tuning, uint32_t lds_reserve, void *stream, ed_basis_t **out)
+                              const ed_tuning_t *tuning, uint32_t lds_reserve, void *stream, ed_basis_t **out,
+                              bool fermion = false)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!out) return set_error(ED_ERR_ARG, "null output handle");
@@ -159,6 +160,22 @@ static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, co
     }
     if (tuning) b->tuning = *tuning;
     b->lds_reserve = lds_reserve;
+    if (fermion) {
+        for (int g = 0; g < b->t.ng; ++g)
+            if (b->t.flip[g]) {
+                delete b;
+                return set_error(ED_ERR_UNSUPPORTED, "element %d of a fermionic group carries a spin flip", g);
+            }
+        if (b->tuning.index_mode != 0 || (b->tuning.table_entry_bytes != 0 && b->tuning.table_entry_bytes != 4)) {
+            delete b;
+            return set_error(ED_ERR_UNSUPPORTED, "fermionic bases use the hash-slot index and 4-byte table entries");
+        }
+        if (b->t.m > 16) {
+            delete b;
+            return set_error(ED_ERR_UNSUPPORTED, "fermionic blocks hold at most 16 orbitals (%d)", b->t.m);
+        }
+        b->fermion = 1;
+    }
     if (b->tuning.block_threads && (b->tuning.block_threads < 64 || b->tuning.block_threads > 1024 ||
                                     b->tuning.block_threads % 64)) {
         delete b;
@@ -199,6 +216,7 @@ static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, co
     dm.P = t.P;
     dm.is_complex = cplx ? 1 : 0;
     dm.trivial_irrep = trivial ? 1 : 0;
+    dm.fermion = b->fermion;
     dm.n_div = (int)b->divs.size();
     b->mean_candidates = sample_mean_candidates(t, n_up);
     const bool two_stage_ok = t.ns >= 2 && t.ns <= 4;
@@ -223,6 +241,12 @@ int ed_build_basis(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irre
                    const ed_tuning_t *tuning, void *stream, ed_basis_t **out)
 {
     return build_basis_common(lat, grp, irrep, n_up, tuning, 0, stream, out);
+}
+
+int ed_build_basis_fermions(const ed_lattice_t *lat, const ed_group_t *grp, const ed_irrep_t *irrep,
+                            int32_t n_particles, const ed_tuning_t *tuning, void *stream, ed_basis_t **out)
+{
+    return build_basis_common(lat, grp, irrep, n_particles, tuning, 0, stream, out, true);
 }
 
 void ed_free_basis(ed_basis_t *b)
@@ -261,6 +285,7 @@ int ed_basis_info(const ed_basis_t *b, ed_basis_info_t *info)
     info->build_ms = b->build_ms;
     info->search_mode = b->staged ? ED_SEARCH_TWO_STAGE : ED_SEARCH_ONE_STAGE;
     info->mean_candidates = b->mean_candidates;
+    info->is_fermion = b->fermion;
     return ED_OK;
 }
 
@@ -306,20 +331,27 @@ int ed_apply_H(const ed_basis_t *b, const double *J, const void *x_dev, void *y_
     return ed_apply_H_xxz(b, J, nullptr, x_dev, y_dev, stream);
 }
 
-int ed_apply_H_timed(const ed_basis_t *b, const double *J, const void *x_dev, void *y_dev, int32_t reps,
-                     double *pack_ms, double *kernel_ms, void *stream)
+int ed_apply_H_timed(const ed_basis_t *b, const double *J, const double *Jz, const void *x_dev, void *y_dev,
+                     int32_t reps, double *pack_ms, double *kernel_ms, void *stream)
 {
     if (!b || !J || !pack_ms || !kernel_ms || (b->db.dim > 0 && (!x_dev || !y_dev)))
         return set_error(ED_ERR_ARG, "null argument");
     if (x_dev == y_dev && b->db.dim > 0) return set_error(ED_ERR_ARG, "x and y must be distinct");
     if (reps < 1 || reps > 1000) return set_error(ED_ERR_ARG, "reps = %d (1..1000)", reps);
-    return ed::launch_apply_timed(b, J, x_dev, y_dev, reps, pack_ms, kernel_ms, stream);
+    return ed::launch_apply_timed(b, J, Jz, x_dev, y_dev, reps, pack_ms, kernel_ms, stream);
+}
+
+static int no_fermions(const ed_basis_t *b)
+{
+    if (b && b->fermion) return set_error(ED_ERR_ARG, "the basis holds fermions: use the *_fermions entry points");
+    return ED_OK;
 }
 
 int ed_apply_H_xxz(const ed_basis_t *b, const double *Jxy, const double *Jz, const void *x_dev, void *y_dev,
                    void *stream)
 {
     if (!b) return set_error(ED_ERR_ARG, "null basis");
+    if (no_fermions(b)) return ED_ERR_ARG;
     if (b->db.dim > 0 && (!x_dev || !y_dev)) return set_error(ED_ERR_ARG, "null vector");
     if (b->db.dim > 0 && x_dev == y_dev) return set_error(ED_ERR_ARG, "x and y must be distinct");
     return ed::launch_apply(b, Jxy, Jz, x_dev, y_dev, stream, 0, nullptr);
@@ -346,23 +378,49 @@ int ed_lanczos(const ed_basis_t *b, const double *J, const void *v0_dev, int32_t
     return ed_lanczos_xxz(b, J, nullptr, v0_dev, n_steps, alpha_host, beta_host, n_done, psi0_dev, stream);
 }
 
-int ed_lanczos_xxz(const ed_basis_t *b, const double *Jxy, const double *Jz, const void *v0_dev, int32_t n_steps,
-                   double *alpha_host, double *beta_host, int32_t *n_done, void *psi0_dev, void *stream)
+int ed_apply_H_fermions(const ed_basis_t *b, const double *t, const double *V, const void *x_dev, void *y_dev,
+                        void *stream)
+{
+    if (!b) return set_error(ED_ERR_ARG, "null basis");
+    if (!b->fermion) return set_error(ED_ERR_ARG, "the basis holds spins: use ed_apply_H");
+    if (b->db.dim > 0 && (!x_dev || !y_dev)) return set_error(ED_ERR_ARG, "null vector");
+    if (b->db.dim > 0 && x_dev == y_dev) return set_error(ED_ERR_ARG, "x and y must be distinct");
+    return ed::launch_apply(b, t, V, x_dev, y_dev, stream, 0, nullptr);
+}
+
+static int lanczos_common(const ed_basis_t *b, const double *J, const double *Jz, const void *v0_dev,
+                          int32_t n_steps, double *alpha_host, double *beta_host, int32_t *n_done, void *psi0_dev,
+                          void *stream)
 {
     if (!b || !n_done) return set_error(ED_ERR_ARG, "null argument");
     if (n_steps < 0) return set_error(ED_ERR_ARG, "n_steps < 0");
     if (n_steps > 0 && (!alpha_host || !beta_host)) return set_error(ED_ERR_ARG, "null alpha/beta");
     if (b->db.dim > 0 && !v0_dev) return set_error(ED_ERR_ARG, "null start vector");
     int nd = 0;
-    int rc = ed::run_lanczos(b, Jxy, Jz, v0_dev, n_steps, alpha_host, beta_host, &nd, psi0_dev, stream);
+    int rc = ed::run_lanczos(b, J, Jz, v0_dev, n_steps, alpha_host, beta_host, &nd, psi0_dev, stream);
     *n_done = nd;
     return rc;
+}
+
+int ed_lanczos_fermions(const ed_basis_t *b, const double *t, const double *V, const void *v0_dev, int32_t n_steps,
+                        double *alpha_host, double *beta_host, int32_t *n_done, void *psi0_dev, void *stream)
+{
+    if (b && !b->fermion) return set_error(ED_ERR_ARG, "the basis holds spins: use ed_lanczos");
+    return lanczos_common(b, t, V, v0_dev, n_steps, alpha_host, beta_host, n_done, psi0_dev, stream);
+}
+
+int ed_lanczos_xxz(const ed_basis_t *b, const double *Jxy, const double *Jz, const void *v0_dev, int32_t n_steps,
+                   double *alpha_host, double *beta_host, int32_t *n_done, void *psi0_dev, void *stream)
+{
+    if (no_fermions(b)) return ED_ERR_ARG;
+    return lanczos_common(b, Jxy, Jz, v0_dev, n_steps, alpha_host, beta_host, n_done, psi0_dev, stream);
 }
 
 static int backward_common(const ed_basis_t *b, const double *J, const void *x_dev, const void *gy_dev, void *gx_dev,
                            double *gJ_host, void *stream, bool static_scratch)
 {
     if (!b) return set_error(ED_ERR_ARG, "null basis");
+    if (b->fermion) return set_error(ED_ERR_UNSUPPORTED, "the adjoint covers spin bases");
     if (b->db.dim > 0 && !gy_dev) return set_error(ED_ERR_ARG, "null gy");
     if (gx_dev) {
         if (gx_dev == gy_dev) return set_error(ED_ERR_ARG, "gx and gy must be distinct");
@@ -416,7 +474,7 @@ int ed_build_multi(const ed_lattice_t *lat, const ed_group_t *grp, int32_t n_sec
     if (!out) return set_error(ED_ERR_ARG, "null output handle");
     *out = nullptr;
     if (!grp || !irreps) return set_error(ED_ERR_ARG, "null argument");
-    if (n_sectors < 1 || n_sectors > 32) return set_error(ED_ERR_UNSUPPORTED, "%d sectors (1..32 supported)", n_sectors);
+    if (n_sectors < 1 || n_sectors > 64) return set_error(ED_ERR_UNSUPPORTED, "%d sectors (1..64 supported)", n_sectors);
     int rc = check_lattice(lat);
     if (rc) return rc;
     for (int k = 0; k < n_sectors; ++k) {
@@ -441,6 +499,11 @@ int ed_build_multi(const ed_lattice_t *lat, const ed_group_t *grp, int32_t n_sec
     // HBM through the caches instead
     const size_t chi_bytes = (size_t)ng * n_sectors * 16;
     mb->chi_in_lds = chi_bytes <= kChiLdsMaxBytes;
+    if (n_sectors > 32 && !mb->chi_in_lds) {
+        delete mb;
+        return set_error(ED_ERR_UNSUPPORTED, "more than 32 sectors need their character table (%zu bytes) in LDS",
+                         chi_bytes);
+    }
     const uint32_t reserve = mb->chi_in_lds ? (uint32_t)((chi_bytes + 15) & ~(size_t)15) : 0u;
     rc = build_basis_common(lat, grp, &trivial, n_up, &tn, reserve, stream, &mb->base);
     if (rc) {

@@ -52,6 +52,8 @@ struct Ctx {
     const uint16_t *rank;
     const uint16_t *pos1;        // two-stage search: source block at position 1 | its state bit offset << 8
     int staged;                  // pos1 is staged
+    const uint64_t *between;     // fermions: orbitals strictly between the two of each bond
+    const uint16_t *g_u;         // fermions: distinct permutation of every group element
 };
 
 __device__ __forceinline__ void lds_copy(char *dst, const void *src, uint32_t bytes)
@@ -87,6 +89,8 @@ __device__ __forceinline__ Ctx<AT> stage(const DevModel &dm, char *lds)
     c.rank = (const uint16_t *)(lds + dm.off_rank);
     c.pos1 = (const uint16_t *)(lds + dm.off_pos1);
     c.staged = dm.staged;
+    c.between = (const uint64_t *)(lds + dm.off_between);
+    c.g_u = (const uint16_t *)(lds + dm.off_gu);
     return c;
 }
 
@@ -105,7 +109,8 @@ __device__ __forceinline__ uint64_t place_block(const Ctx<AT> &c, uint32_t u, in
 {
     if (ActTraits<AT>::kPos) {
         const uint32_t img = e & ((1u << ActTraits<AT>::kPosShift) - 1u);
-        const uint32_t pos = e >> ActTraits<AT>::kPosShift;
+        // 4-byte entries keep bits 24-31 for fermionic sign parities
+        const uint32_t pos = sizeof(AT) == 4 ? (e >> 16) & 0xFFu : e >> ActTraits<AT>::kPosShift;
         // position and block width are below 2^24: full-rate 24-bit multiply
         return (uint64_t)img << ((uint32_t)(c.N - c.m) - __umul24(pos, (uint32_t)c.m));
     }
@@ -349,6 +354,45 @@ __device__ __forceinline__ uint64_t find_rep_staged(const Ctx<AT> &c, uint64_t s
     return best;
 }
 
+// Fermi sign of a group element on an occupation pattern (sec. "Discussion":
+// fermions in the occupation-number basis need a sign besides the
+// representative).  The element permutes orbitals; the sign is (-1) to the
+// number of occupied orbital pairs whose order it reverses.  Sublattice
+// stability splits that count: pairs in different source blocks are reversed
+// iff their target blocks are (all occupied pairs of the two blocks at once),
+// pairs in one chunk come from the parity bit of the chunk's table entry, and
+// pairs in two chunks of one block from the chunk images: for the chunks in
+// source order, the pairs an image forms with the images of the earlier
+// chunks that land below it.  Returns the parity (0 or 1); 4-byte entries.
+template <typename AT>
+__device__ __forceinline__ uint32_t fermi_parity(const Ctx<AT> &c, uint32_t u, uint64_t s)
+{
+    static_assert(sizeof(AT) == 4, "fermionic tables use 4-byte entries");
+    uint32_t par = 0;
+    uint64_t seen = 0;   // target blocks of the earlier source blocks with odd occupation
+    for (int X = 0; X < c.ns; ++X) {
+        const uint32_t sx = (uint32_t)(s >> (c.N - (X + 1) * c.m)) & c.mmask;
+        const AT *t = c.act + ((size_t)(u * c.ns + X) * c.nc << c.cb);
+        uint32_t earlier = 0, pos = 0;
+        for (int k = c.nc - 1; k >= 0; --k) {   // chunk nc-1 holds the block's first orbitals
+            const uint32_t e = t[(k << c.cb) | ((sx >> (k * c.cb)) & c.cmask)];
+            const uint32_t img = e & 0xFFFFu;
+            uint32_t px = earlier;               // px bit j: parity of earlier image bits at or below j
+            px ^= px << 1;
+            px ^= px << 2;
+            px ^= px << 4;
+            px ^= px << 8;
+            par ^= (e >> 31) ^ ((uint32_t)__popc(img & (px << 1)) & 1u);
+            earlier |= img;
+            if (k == 0) pos = (e >> 16) & 0xFFu;
+        }
+        const uint32_t odd = (uint32_t)__popc(sx) & 1u;
+        par ^= odd & ((uint32_t)__popcll(seen >> (pos + 1)) & 1u);
+        seen |= (uint64_t)odd << pos;
+    }
+    return par;
+}
+
 constexpr int kStagedFlag = 128;   // NSC bit selecting the two-stage search
 
 // NSC = NS * 8 + NC: sublattices and chunks fixed at compile time (0 = read
@@ -395,14 +439,18 @@ __device__ __forceinline__ uint64_t slot_of_state(uint64_t s, int log2n)
 }
 
 // first 16 bytes of a slot: {key, x} (real) or {key, -} (complex).  Slot
-// reads are random and rarely reused, so they are issued as non-temporal
-// loads, which keeps them from displacing the streamed basis and vectors in
-// the caches.
+// reads are random and rarely reused, so the real slots are read with
+// non-temporal loads, which keeps them from displacing the streamed basis and
+// vectors in the caches.  A complex slot is two 16-byte reads of one line:
+// with a non-temporal first read the line is often gone when the second
+// arrives (1.20 lines per term on the 36-site momentum sector, against 1.08
+// with ordinary loads), so both are ordinary loads.
 template <bool CPLX>
 __device__ __forceinline__ ulonglong2 load_slot(const char *slots, uint64_t sl)
 {
     typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
-    const u64x2 v = __builtin_nontemporal_load((const u64x2 *)(slots + (sl << (CPLX ? 5 : 4))));
+    const u64x2 *p = (const u64x2 *)(slots + (sl << (CPLX ? 5 : 4)));
+    const u64x2 v = CPLX ? *p : __builtin_nontemporal_load(p);
     return make_ulonglong2(v.x, v.y);
 }
 
@@ -410,7 +458,7 @@ __device__ __forceinline__ ulonglong2 load_slot(const char *slots, uint64_t sl)
 __device__ __forceinline__ double2 load_slot_value(const char *slots, uint64_t sl)
 {
     typedef double f64x2 __attribute__((ext_vector_type(2)));
-    const f64x2 v = __builtin_nontemporal_load((const f64x2 *)(slots + (sl << 5) + 16));
+    const f64x2 v = *(const f64x2 *)(slots + (sl << 5) + 16);
     return make_double2(v.x, v.y);
 }
 

@@ -69,6 +69,11 @@ std::vector<uint32_t> divisors_of(uint32_t n);
 //   div  : double [n_div] sqrt of the divisors of |G|, then their inverses
 //   bonds: {uint64 mask, double J/2} [nb]
 //   rank : uint16 [P]      rank of a top-block value (Limits index only)
+// Fermionic bases (orbital occupations) also stage
+//   between: uint64 [nb]   orbitals strictly between the two of each bond
+//   g_u    : uint16 [ng]   distinct-permutation index of every element
+// and their 4-byte action entries carry, in bit 31, the parity of the
+// orbital pairs of the chunk whose order the permutation reverses.
 struct DevModel {
     int N, ns, m, ng, nu, nb;
     uint32_t P;
@@ -78,9 +83,10 @@ struct DevModel {
     int chunk_bits, n_chunks;
     int act_bytes;             // 1, 2 or 4 bytes per action-table entry
     int staged;                // the pos1 table is staged: two-stage search available
+    int fermion;               // occupation-number basis of fermions
     const char *blob;
     uint32_t off_rep, off_sym, off_act, off_shift, off_chi, off_div, off_divval, off_bonds, off_rank,
-        off_pos1, lds_total;
+        off_pos1, off_between, off_gu, lds_total;
 };
 
 struct DevBasis {
@@ -125,6 +131,7 @@ struct ed_basis {
     uint32_t lds_reserve = 0;      // LDS bytes kept free for kernels that stage more
     double mean_candidates = 0.0;  // host Alg. 2 on random configurations
     int staged = 0;                // the H.v kernels run the two-stage search
+    int fermion = 0;               // fermions in the occupation-number basis
     // Lanczos workspace, kept between calls and freed with the handle
     struct {
         double *vec[3] = {nullptr, nullptr, nullptr};
@@ -166,8 +173,8 @@ int launch_basis_build(ed_basis *b, void *stream);
 int multi_lanes_per_row(const ed_multi *mb);
 int launch_apply(const ed_basis *b, const double *J, const double *Jz, const void *x, void *y, void *stream, int stats_mode,
                  unsigned long long *stats_dev);
-int launch_apply_timed(const ed_basis *b, const double *J, const void *x, void *y, int reps, double *pack_ms,
-                       double *kernel_ms, void *stream);
+int launch_apply_timed(const ed_basis *b, const double *J, const double *Jz, const void *x, void *y, int reps,
+                       double *pack_ms, double *kernel_ms, void *stream);
 int launch_backward_J(const ed_basis *b, const double *J, const void *x, const void *gy, double *gJ_host, void *stream,
                       bool static_scratch);
 int run_lanczos(const ed_basis *b, const double *J, const double *Jz, const void *v0, int n_steps, double *alpha, double *beta,

@@ -29,7 +29,12 @@ namespace ed {
 // w = H v - beta_prev v_prev with per-block <v, w> partial sums.
 // ---------------------------------------------------------------------------
 
-template <bool CPLX, typename AT, int INDEX, int MODE, int NS>
+// FERMI: fermions in the occupation-number basis (4-byte tables, hash
+// index): a flip of bond b is the hop -t_b (c+_p c_q + h.c.) with sign
+// (-1)^(occupied orbitals between p and q) times the Fermi sign of the
+// element mapping the hopped configuration to its representative, and the
+// diagonal is sum_b V_b n_p n_q (jhalf = -t_b, jzhalf = V_b).
+template <bool CPLX, typename AT, int INDEX, int MODE, int NS, bool FERMI = false>
 __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const typename Scalar<CPLX>::T *__restrict__ x,
                                                 typename Scalar<CPLX>::T *__restrict__ y,
                                                 const typename Scalar<CPLX>::T *__restrict__ vprev, double *partials,
@@ -60,6 +65,13 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
         am.w2 = nb > 128 ? bond_word(c, s, 2, nb) : 0ull;
         am.w3 = nb > 192 ? bond_word(c, s, 3, nb) : 0ull;
         const int n_terms = row_ok ? __popcll(am.w0) + __popcll(am.w1) + __popcll(am.w2) + __popcll(am.w3) : 0;
+        double fdiag = 0.0;   // fermions: sum_b V_b n_p n_q
+        if constexpr (FERMI) {
+            for (int k = 0; k < nb; ++k) {
+                const uint64_t bm = c.bonds[k].mask;
+                if ((s & bm) == bm) fdiag += c.bonds[k].jzhalf;
+            }
+        }
         if (INDEX == IDX_HASH && MODE != 1) {
             // software pipeline: the slot of the next term is requested before
             // the current term is resolved, so the random read overlaps the
@@ -69,11 +81,20 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
             double jh_nx = 0.0;
             ulonglong2 q_nx = make_ulonglong2(0ull, 0ull);
             double2 v_nx = make_double2(0.0, 0.0);   // complex: home slot's amplitude
+            // fermions: hop sign times the Fermi sign of the element found
+            auto fermi_amp = [&](int bi, uint64_t sp, uint32_t g, double jh) -> double {
+                if constexpr (FERMI) {
+                    const uint32_t par = ((uint32_t)__popcll(s & c.between[bi]) & 1u) ^ fermi_parity(c, c.g_u[g], sp);
+                    return par ? -jh : jh;
+                }
+                return jh;
+            };
             if (n_terms > 0) {
-                const BondLds bd = c.bonds[pop_bond(am)];
+                const int bi = pop_bond(am);
+                const BondLds bd = c.bonds[bi];
                 anti_sum += bd.jzhalf;
-                jh_nx = bd.jhalf;
                 r_nx = rep_search<AT, NS>(c, s ^ bd.mask, g_nx);
+                jh_nx = fermi_amp(bi, s ^ bd.mask, g_nx, bd.jhalf);
                 sl_nx = slot_of_state(r_nx, db.slot_log2);
                 q_nx = load_slot<CPLX>(db.slots, sl_nx);
                 if (CPLX) v_nx = load_slot_value(db.slots, sl_nx);
@@ -85,10 +106,11 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
                 const ulonglong2 q = q_nx;
                 const double2 v = v_nx;
                 if (term + 1 < n_terms) {
-                    const BondLds bd = c.bonds[pop_bond(am)];
+                    const int bi = pop_bond(am);
+                    const BondLds bd = c.bonds[bi];
                     anti_sum += bd.jzhalf;
-                    jh_nx = bd.jhalf;
                     r_nx = rep_search<AT, NS>(c, s ^ bd.mask, g_nx);
+                    jh_nx = fermi_amp(bi, s ^ bd.mask, g_nx, bd.jhalf);
                     sl_nx = slot_of_state(r_nx, db.slot_log2);
                     q_nx = load_slot<CPLX>(db.slots, sl_nx);
                     if (CPLX) v_nx = load_slot_value(db.slots, sl_nx);
@@ -147,7 +169,7 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
             }
         }
         if (MODE == 1 || !row_ok) continue;
-        const double d = jsum_quarter - anti_sum;
+        const double d = FERMI ? fdiag : jsum_quarter - anti_sum;
         if (CPLX) {
             const double2 xi = *(const double2 *)&x[i];
             double2 out;
@@ -402,7 +424,13 @@ __global__ void __launch_bounds__(256) k_basis_enum(DevModel dm, BuildParams bp,
                             }
                             if (img == sgm) {
                                 ++nstab;
-                                if (!dm.trivial_irrep) {
+                                // the symmetrised state survives iff chi(g) equals the action's
+                                // sign on the stabiliser: 1 for spins, the Fermi sign for fermions
+                                double sign = 1.0;
+                                if constexpr (sizeof(AT) == 4) {
+                                    if (dm.fermion && fermi_parity(c, (ent >> 16) & 0x7FFFu, sgm)) sign = -1.0;
+                                }
+                                if (!dm.trivial_irrep || sign < 0.0) {
                                     double cr, ci;
                                     if (dm.is_complex) {
                                         cr = c.chi[2 * g];
@@ -411,7 +439,7 @@ __global__ void __launch_bounds__(256) k_basis_enum(DevModel dm, BuildParams bp,
                                         cr = c.chi[g];
                                         ci = 0.0;
                                     }
-                                    if (fabs(cr - 1.0) > 1e-9 || fabs(ci) > 1e-9) compat = false;
+                                    if (fabs(cr - sign) > 1e-9 || fabs(ci) > 1e-9) compat = false;
                                 }
                             }
                         }
@@ -711,6 +739,19 @@ static int upload_tables(ed_basis *b, hipStream_t st)
     for (int u = 0; u < (int)pos1.size(); ++u)
         for (int X = 0; X < ns; ++X)
             if (t.u_tgt[(size_t)u * ns + X] == 1) pos1[u] = (uint16_t)(X | (t.N - (X + 1) * m) << 8);
+    // fermions: the orbitals strictly between the two of each bond, and the
+    // distinct permutation of every group element
+    std::vector<uint64_t> between(b->fermion ? std::max(t.nb, 1) : 0, 0ull);
+    for (int k = 0; k < (int)between.size() && k < t.nb; ++k) {
+        const int lo = std::min(t.bonds[2 * k], t.bonds[2 * k + 1]), hi = std::max(t.bonds[2 * k], t.bonds[2 * k + 1]);
+        for (int i = lo + 1; i < hi; ++i) between[k] |= 1ull << (t.N - 1 - i);
+    }
+    std::vector<uint16_t> gu(b->fermion ? t.ng : 0);
+    for (size_t g = 0; g < gu.size(); ++g) gu[g] = t.g_u[g];
+    // fermions: image bit of every single orbital of a block, per permutation
+    std::vector<uint8_t> img_bit(b->fermion ? (size_t)t.nu * ns * m : 0);
+    for (size_t ux = 0; ux < (b->fermion ? (size_t)t.nu * ns : 0); ++ux)
+        for (int j = 0; j < m; ++j) img_bit[ux * m + j] = (uint8_t)__builtin_ctz(t.act[ux * P + (1u << j)]);
     // rank of every top-block value, staged only for the Limits index
     std::vector<uint16_t> rank(b->db.index_mode == IDX_LIMITS ? P : 1, 0);
     if (b->db.index_mode == IDX_LIMITS)
@@ -740,6 +781,8 @@ static int upload_tables(ed_basis *b, hipStream_t st)
         dm.off_bonds = put(bz.data(), bz.size() * sizeof(BondLds));
         dm.off_rank = put(rank.data(), rank.size() * 2);
         dm.off_pos1 = put(pos1.data(), pos1.size() * 2);
+        dm.off_between = put(between.data(), between.size() * 8);
+        dm.off_gu = put(gu.data(), gu.size() * 2);
         // chunked action table [nu][ns][nc][2^cb]; wide entries of chunk 0
         // also carry the target block index
         const size_t ent = (size_t)t.nu * ns * nc << cb;
@@ -753,6 +796,16 @@ static int upload_tables(ed_basis *b, hipStream_t st)
                         for (uint32_t v = 0; v < (1u << width); ++v) {
                             uint32_t img = t.act[((size_t)u * ns + X) * P + (v << (k * cb))];
                             if (esz > 1 && k == 0) img |= (uint32_t)t.u_tgt[(size_t)u * ns + X] << pos_shift;
+                            if (b->fermion) {
+                                // orbital pairs of the chunk whose order u reverses: bit a above
+                                // bit c of the substate (a is the earlier orbital) landing below
+                                const uint8_t *ib = &img_bit[((size_t)u * ns + X) * m + k * cb];
+                                uint32_t par = 0;
+                                for (int a = 0; a < width; ++a)
+                                    for (int c2 = 0; c2 < a; ++c2)
+                                        if ((v >> a & 1u) && (v >> c2 & 1u) && ib[a] < ib[c2]) par ^= 1u;
+                                img |= par << 31;
+                            }
                             const size_t idx = ((((size_t)u * ns + X) * nc + k) << cb) | v;
                             memcpy(&act[idx * esz], &img, esz);   // little endian: low bytes
                         }
@@ -771,7 +824,8 @@ static int upload_tables(ed_basis *b, hipStream_t st)
     // LDS budget, a wide entry if it fits at that chunk count; for a given
     // chunk count the narrowest equal split is the smallest table.
     const int wide = m <= 12 ? 2 : 4;
-    int want_esz = b->tuning.table_entry_bytes;
+    // fermionic sign parities live in bit 31 of 4-byte entries
+    int want_esz = b->fermion ? 4 : b->tuning.table_entry_bytes;
     if (want_esz == 1 && m > 8) want_esz = wide;
     if (want_esz == 2 && m > 12) want_esz = 4;
     int cb = m, esz = want_esz ? want_esz : wide;
@@ -822,6 +876,27 @@ int upload_couplings(const ed_basis *bc, const double *J, const double *Jz, hipS
 {
     ed_basis *b = const_cast<ed_basis *>(bc);
     const Tables &t = b->t;
+    if (b->fermion) {
+        // fermions: J holds the hoppings t_b, Jz the density couplings V_b
+        // (nullptr: 0); the flip term of bond b carries -t_b, the diagonal
+        // sum_b V_b n_p n_q
+        std::vector<double> key(J, J + t.nb);
+        for (int k = 0; k < t.nb; ++k) key.push_back(Jz ? Jz[k] : 0.0);
+        *jsum_quarter = 0.0;
+        if (b->J_cache == key) return ED_OK;
+        std::vector<BondLds> bz((size_t)std::max(t.nb, 1));
+        for (int k = 0; k < t.nb; ++k) {
+            const int p = t.bonds[2 * k], q = t.bonds[2 * k + 1];
+            bz[k].mask = (1ull << (t.N - 1 - p)) | (1ull << (t.N - 1 - q));
+            bz[k].jhalf = -J[k];
+            bz[k].jzhalf = Jz ? Jz[k] : 0.0;
+        }
+        char *dst = (char *)b->dm.blob + b->dm.off_bonds;
+        HIP_TRY(hipMemcpyAsync(dst, bz.data(), (size_t)t.nb * sizeof(BondLds), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        b->J_cache = key;
+        return ED_OK;
+    }
     if (!Jz) Jz = J;
     double js = 0.0;
     for (int k = 0; k < t.nb; ++k) js += Jz[k];
@@ -1088,12 +1163,12 @@ static int pack_input(const ed_basis *b, const void *x, hipStream_t st)
     return ED_OK;
 }
 
-template <bool CPLX, typename AT, int INDEX, int MODE, int NS>
+template <bool CPLX, typename AT, int INDEX, int MODE, int NS, bool FERMI = false>
 static int apply_impl(const ed_basis *b, const void *x, void *y, const void *vprev, double *partials,
                       unsigned long long *stats, const LzState *lz, double jsq, hipStream_t st)
 {
     using T = typename Scalar<CPLX>::T;
-    auto kern = k_apply<CPLX, AT, INDEX, MODE, NS>;
+    auto kern = k_apply<CPLX, AT, INDEX, MODE, NS, FERMI>;
     int grid, threads;
     size_t lds = b->dm.lds_total;
     launch_cfg(b, kern, lds, &grid, &threads);
@@ -1162,6 +1237,11 @@ template <int MODE>
 static int apply_dispatch(const ed_basis *b, const void *x, void *y, const void *vprev, double *partials,
                           unsigned long long *stats, const LzState *lz, double jsq, hipStream_t st)
 {
+    if (b->fermion) {   // 4-byte tables, hash index, search loops read at run time
+        if (b->dm.is_complex)
+            return apply_impl<true, uint32_t, IDX_HASH, MODE, 0, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
+        return apply_impl<false, uint32_t, IDX_HASH, MODE, 0, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    }
     if (b->dm.act_bytes == 1) return apply_dispatch_t<MODE, uint8_t>(b, x, y, vprev, partials, stats, lz, jsq, st);
     if (b->dm.act_bytes == 2) return apply_dispatch_t<MODE, uint16_t>(b, x, y, vprev, partials, stats, lz, jsq, st);
     return apply_dispatch_t<MODE, uint32_t>(b, x, y, vprev, partials, stats, lz, jsq, st);
@@ -1189,14 +1269,15 @@ int launch_apply(const ed_basis *b, const double *J, const double *Jz, const voi
 
 // ed_apply_H repeated reps times, with HIP events on the stream around the
 // amplitude scatter and around the H.v kernel of every launch
-int launch_apply_timed(const ed_basis *b, const double *J, const void *x, void *y, int reps, double *pack_ms,
-                       double *kernel_ms, void *stream)
+int launch_apply_timed(const ed_basis *b, const double *J, const double *Jz, const void *x, void *y, int reps,
+                       double *pack_ms, double *kernel_ms, void *stream)
 {
     hipStream_t st = (hipStream_t)stream;
     int rc = check_couplings(b, J);
+    if (!rc && Jz) rc = check_couplings(b, Jz);
     if (rc) return rc;
     double jsq = 0.0;
-    rc = upload_couplings(b, J, nullptr, st, &jsq);
+    rc = upload_couplings(b, J, Jz, st, &jsq);
     if (rc) return rc;
     *pack_ms = 0.0;
     *kernel_ms = 0.0;

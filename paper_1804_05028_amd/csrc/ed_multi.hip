@@ -15,12 +15,13 @@
 // Layout: vectors are complex128 [dim][K], sector index fastest, so the K
 // amplitudes of a target are one contiguous read.  The slot table's value
 // field holds the row index (low 32 bits) and the row's sector mask (high 32
-// bits), so one 16-byte probe returns index, norm and compatibility.
+// bits), so one 16-byte probe returns index, norm and compatibility; with
+// more than 32 sectors the target's mask is read from the per-row mask array.
 #include "ed_device.hpp"
 
 namespace ed {
 
-constexpr int kMaxSectors = 32;
+constexpr int kMaxSectors = 64;
 constexpr int kMlzThreads = 256;
 
 struct MultiDev {
@@ -216,7 +217,9 @@ __global__ void __launch_bounds__((multi_block_bound<KB, SPLIT>()))
                 q = load_slot<false>(db.slots, sl);
             }
             const bool found = q.x != kEmpty;
-            const uint64_t mij = found ? (mi & (q.y >> 32)) : 0ull;   // bit koff + SPLIT k: local sector k
+            // bit koff + SPLIT k: local sector k
+            const uint64_t mj = K > 32 ? (found ? md.masks[q.y & 0xFFFFFFFFull] : 0ull) : (q.y >> 32);
+            const uint64_t mij = found ? (mi & mj) : 0ull;
             // the target's amplitudes are requested before the next term's
             // search, which hides their latency
             // registers allow holding the next row's amplitudes (split rows
@@ -526,6 +529,8 @@ int multi_lanes_per_row(const ed_multi *mb)
     // a character table read from HBM needs an instance with at most 4
     // sectors per lane, or 8 per lane on a split row
     if (!mb->chi_in_lds) t = std::max(t, K <= 4 ? 1 : (K <= 16 ? 2 : 4));
+    // more than 32 sectors: 4 lanes of at most 16 sectors each
+    if (K > 32) t = 4;
     return t;
 }
 
@@ -544,11 +549,15 @@ static int multi_launch_kb(const ed_multi *mb, const void *x, void *y, const voi
     }
     if (MODE == 0 && split == 4) {
         if (kh <= 4) ED_KB(4, 4);
-        ED_KB(8, 4);
+        if (kh <= 8) ED_KB(8, 4);
+        ED_KB(16, 4);
     }
     if (kh <= 4) ED_KB(4, 1);
     if (kh <= 8) ED_KB(8, 1);
     if (kh <= 16) ED_KB(16, 1);
+    if constexpr (MODE == 1) {   // term counts of more than 32 sectors (lanes of 4 run the H.v)
+        if (kh > 32) ED_KB(64, 1);
+    }
     ED_KB(32, 1);
 #undef ED_KB
 }
@@ -598,6 +607,9 @@ int multi_setup(ed_multi *mb, void *stream)
     const int K = mb->K, ng = b->t.ng;
     const int64_t D = b->db.dim;
     if (K < 1 || K > kMaxSectors) return set_error(ED_ERR_UNSUPPORTED, "%d sectors (1..%d supported)", K, kMaxSectors);
+    if (K > 32 && !mb->chi_in_lds)
+        return set_error(ED_ERR_UNSUPPORTED, "more than 32 sectors need their character table (%zu bytes) in LDS",
+                         (size_t)ng * K * 16);
     if (b->db.index_mode != 0) return set_error(ED_ERR_ARG, "batched sectors use the hash-slot index");
     // trivial-character masks per element and the character table [ng][K]
     std::vector<uint64_t> triv(ng, 0);

@@ -32,11 +32,13 @@ class Basis:
     representative search) and lanczos_direct (1 = no graph replay).
     """
 
+    _build = staticmethod(L.ed_build_basis)
+
     def __init__(self, n_sites, bonds, n_sublat, perm, flip, chi, n_up, tuning=None):
         _require_gpu()
         self.arrays = L.ModelArrays(n_sites, bonds, n_sublat, perm, flip, chi)
         self.n_up = int(n_up)
-        self.handle = L.ed_build_basis(self.arrays, n_up, tuning, _stream())
+        self.handle = self._build(self.arrays, n_up, tuning, _stream())
         self.dim = L.ed_basis_dim(self.handle)
         self.is_complex = L.ed_basis_is_complex(self.handle)
         self.n_bonds = int(self.arrays.bonds.shape[0])
@@ -104,12 +106,15 @@ class Basis:
     def stats(self):
         return L.ed_apply_H_stats(self.handle, _stream())
 
-    def apply_timed(self, J, x, out=None, reps=5):
-        """reps launches of y = H x; returns (y, mean scatter ms, mean H.v kernel ms)."""
+    def apply_timed(self, J, x, out=None, reps=5, Jz=None):
+        """reps launches of y = H x; returns (y, mean scatter ms, mean H.v kernel ms).
+        For fermionic bases J and Jz are the hoppings t and interactions V."""
         self._check_vec(x, "x")
         y = self.empty() if out is None else out
         self._check_vec(y, "out")
-        pack_ms, kernel_ms = L.ed_apply_H_timed(self.handle, np.asarray(J, np.float64), x, y, reps, _stream())
+        pack_ms, kernel_ms = L.ed_apply_H_timed(self.handle, np.asarray(J, np.float64),
+                                                None if Jz is None else np.asarray(Jz, np.float64), x, y, reps,
+                                                _stream())
         return y, pack_ms, kernel_ms
 
     def lanczos(self, J, v0, n_steps, want_psi0=False, Jz=None):
@@ -131,6 +136,43 @@ class Basis:
         gJ = L.ed_apply_H_backward(self.handle, np.asarray(J, np.float64), x if want_gJ else None, gy, gx,
                                    want_gJ, _stream())
         return gx, gJ
+
+
+class FermionBasis(Basis):
+    """A sector of spinless fermions (or of spinful ones written as two
+    orbitals per site) in the occupation-number basis: orbitals take the
+    place of sites and n_particles that of n_up; the group carries no spin
+    flip.  H = sum_b [-t_b (c+_p c_q + h.c.) + V_b n_p n_q]."""
+
+    _build = staticmethod(L.ed_build_basis_fermions)
+
+    def __init__(self, n_orb, bonds, n_sublat, perm, chi, n_particles, tuning=None):
+        perm = np.asarray(perm)
+        super().__init__(n_orb, bonds, n_sublat, perm, np.zeros(perm.shape[0], np.uint8), chi, n_particles, tuning)
+
+    @classmethod
+    def from_workload(cls, w, tuning=None):
+        c = w.cluster
+        return cls(c.n_sites, c.bonds, c.n_sublat, c.perm, w.chi, w.n_up, tuning)
+
+    def apply(self, t, x, out=None, V=None):
+        self._check_vec(x, "x")
+        y = self.empty() if out is None else out
+        self._check_vec(y, "out")
+        L.ed_apply_H_fermions(self.handle, np.asarray(t, np.float64), None if V is None else np.asarray(V, np.float64),
+                              x, y, _stream())
+        return y
+
+    def lanczos(self, t, v0, n_steps, want_psi0=False, V=None):
+        self._check_vec(v0, "v0")
+        psi = self.empty() if want_psi0 else None
+        a, b, n = L.ed_lanczos_fermions(self.handle, np.asarray(t, np.float64),
+                                        None if V is None else np.asarray(V, np.float64), v0, n_steps, psi, _stream())
+        ev, _ = L.ed_tridiag_eigh(a, b, want_vec=False) if n else (np.array([]), None)
+        return dict(alpha=a, beta=b, n_done=n, eigenvalues=ev, psi0=psi)
+
+    def backward(self, *args, **kwargs):
+        raise NotImplementedError("the adjoint covers spin bases")
 
 
 class MultiBasis:

@@ -156,3 +156,49 @@ def test_benchmark_instances_match_oracle(name, make, tune, chunks, chi_lds, lan
         assert np.linalg.norm(y[sel, k] - ref) <= RTOL * np.linalg.norm(ref), (name, k)
         assert np.abs(y[sel, k] - ref).max() <= 10 * RTOL * max(np.abs(ref).max(), 1e-300), (name, k)
         assert np.all(y[~sel, k] == 0)
+
+
+
+MANY = [("chain36_k36", 36, 3, 4), ("chain40_k40", 40, 3, 4)]
+
+
+@pytest.mark.parametrize("name,n,n_up,period", MANY, ids=[m[0] for m in MANY])
+def test_more_than_32_sectors(name, n, n_up, period):
+    """All momenta of a 36- and a 40-site ring in one batched basis: sector
+    masks beyond bit 31 come from the per-row mask array; every sector of
+    H.v against the oracle, term counts against the single-sector path, and
+    the batched Lanczos (one graph-replayed call for all sectors) against the
+    dense spectrum of each sector."""
+    ed = _ed()
+    c = lat.chain(n, superlattice_period=period)
+    ws = [wl.Workload(f"{name}_{k}", c, lat.characters(c, k), n_up, np.ones(c.n_bonds)) for k in range(n)]
+    mb = ed.MultiBasis.from_workloads(ws)
+    try:
+        info = mb.info()
+        assert info["n_sectors"] == n and info["lanes_per_row"] == 4 and info["chi_in_lds"] == 1
+        x = _x(mb.dim, mb.K, 71)
+        y = mb.apply(ws[0].J, torch.as_tensor(x).cuda()).cpu().numpy()
+        masks = mb.masks()
+        terms, _ = mb.stats()
+        res = mb.lanczos(ws[0].J, torch.as_tensor(x).cuda(), 160)
+    finally:
+        mb.close()
+    total = 0
+    for k, w in enumerate(ws):
+        sel = ((masks >> np.uint64(k)) & np.uint64(1)).astype(bool)
+        m = bf.Model.from_workload(w)
+        st, stab = bf.basis(m, w.n_up)
+        assert sel.sum() == len(st), k
+        total += len(st)
+        assert np.all(y[~sel, k] == 0)
+        if len(st) == 0:
+            assert res["n_done"][k] == 0
+            continue
+        ref, kept, _ = bf.apply(m, st, stab, x[sel, k])
+        assert np.linalg.norm(y[sel, k] - ref) <= RTOL * np.linalg.norm(ref), k
+        assert terms[k] == len(st) + kept, k
+        H = bf.dense_matrix(m, st)
+        e0 = np.linalg.eigvalsh((H + H.conj().T) / 2)[0]
+        assert abs(res["eigenvalues"][k][0] - e0) <= 1e-10 * max(1.0, abs(e0)), k
+    from math import comb
+    assert total == comb(n, n_up)

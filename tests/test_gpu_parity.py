@@ -143,10 +143,11 @@ def test_lanczos_eigenvalues(built, name):
     st, stab = bf.basis(m, w.n_up)
     v0 = vec.normal_vector(len(st), complex_=w.is_complex)
     n_steps = min(200, len(st) + 5)
-    ref = olz.lanczos(lambda v: bf.apply(m, st, stab, v)[0], v0, n_steps)
+    # the oracle's sector matrix (row form, equal to its scatter H.v) drives
+    # the oracle recurrence and gives the dense spectrum
+    H = bf.dense_matrix(m, st)
+    ref = olz.lanczos(lambda v: H @ v, v0, n_steps)
     res = b.lanczos(w.J, torch.as_tensor(v0).cuda(), n_steps)
-    # dense spectrum of the (small) sector as the exact reference
-    H = np.stack([bf.apply(m, st, stab, e.astype(np.complex128))[0] for e in np.eye(len(st))], 1)
     exact = np.linalg.eigvalsh((H + H.conj().T) / 2)
     conv = olz.converged_ritz(res["alpha"], res["beta"])
     assert len(conv) >= 1
@@ -185,7 +186,7 @@ def test_lanczos_breakdown_small_sector():
         res = b.lanczos(w.J, torch.as_tensor(vec.normal_vector(D)).cuda(), 100)
         m = bf.Model.from_workload(w)
         st, stab = bf.basis(m, 5)
-        H = np.stack([bf.apply(m, st, stab, e)[0] for e in np.eye(D)], 1)
+        H = bf.dense_matrix(m, st).real
         assert abs(res["eigenvalues"][0] - np.linalg.eigvalsh(H)[0]) < 1e-10
         ref = olz.lanczos(lambda v: bf.apply(m, st, stab, v)[0], vec.normal_vector(D), 100)
         assert res["n_done"] == ref["n_done"]
@@ -233,3 +234,36 @@ def test_empty_sector():
     finally:
         b.close()
     _ = math
+
+
+NEAR_BREAKDOWN = [
+    # (cluster, momentum, n_up): sectors of two and three states, where the
+    # Krylov space is exhausted and beta falls to rounding level, ~1e-16 of
+    # the scale, before orthogonality can be lost
+    ("ring4_k0", 4, 0, 2), ("ring4_k2", 4, 2, 2), ("ring6_k0_n2", 6, 0, 2), ("ring6_k3_n3", 6, 3, 3),
+]
+
+
+@pytest.mark.parametrize("name,n,k,n_up", NEAR_BREAKDOWN, ids=[c[0] for c in NEAR_BREAKDOWN])
+def test_lanczos_near_breakdown_matches_oracle_step_count(name, n, k, n_up):
+    ed = _ed()
+    c = lat.chain(n, superlattice_period=2)
+    w = wl.Workload(name, c, lat.characters(c, k), n_up, np.ones(c.n_bonds))
+    b = ed.Basis.from_workload(w)
+    try:
+        D = b.dim
+        assert 2 <= D <= 4, D
+        m = bf.Model.from_workload(w)
+        st, _ = bf.basis(m, n_up)
+        H = bf.dense_matrix(m, st)
+        v0 = vec.normal_vector(D, seed=9, complex_=b.is_complex)
+        ref = olz.lanczos(lambda v: H @ v, v0, 20)
+        res = b.lanczos(w.J, torch.as_tensor(v0).cuda(), 20)
+        print(f"[breakdown] {name}: D={D} n_done={res['n_done']} oracle {ref['n_done']} "
+              f"last beta {res['beta'][res['n_done'] - 1]:.2e}", flush=True)
+        assert res["n_done"] == ref["n_done"] <= D
+        assert res["beta"][res["n_done"] - 1] <= 1e-12 * max(np.abs(res["alpha"]).max(), res["beta"].max())
+        exact = np.linalg.eigvalsh((H + H.conj().T) / 2)
+        assert np.abs(np.sort(res["eigenvalues"]) - exact[:len(res["eigenvalues"])]).max() < 1e-12
+    finally:
+        b.close()

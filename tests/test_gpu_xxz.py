@@ -57,7 +57,7 @@ def test_xxz_apply_and_lanczos_match_oracle(name, w, Jz):
         y = b.apply(w.J, torch.as_tensor(x).cuda(), Jz=Jz).cpu().numpy()
         ref, _, _ = bf.apply(m, st, stab, x)
         assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref), name
-        H = np.stack([bf.apply(m, st, stab, e.astype(complex))[0] for e in np.eye(len(st))], 1)
+        H = bf.dense_matrix(m, st)
         e_dense = np.linalg.eigvalsh((H + H.conj().T) / 2)[0]
         res = b.lanczos(w.J, torch.as_tensor(vec.normal_vector(len(st), seed=4, complex_=b.is_complex)).cuda(),
                         min(len(st), 150), Jz=Jz)

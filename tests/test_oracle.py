@@ -244,3 +244,19 @@ def test_hashed_vector_and_row_sampling_consistency():
     yr, _, _, _ = bf.rows_apply(m, rows, lambda s: vec.hashed_amplitudes(s, salt=1))
     idx = np.searchsorted(st, rows)
     assert np.abs(yr - y[idx]).max() < 1e-12
+
+
+def test_dense_row_matrix_equals_scatter_columns():
+    """dense_matrix (row form, one pass) equals the matrix whose columns are
+    the scatter H.v of unit vectors, for real and complex sectors, spins and
+    fermions."""
+    c = lat.chain(8)
+    for k in (0, 1, 4):
+        m = bf.Model(8, c.perm, c.flip, lat.characters(c, k), c.bonds, np.ones(8))
+        st, stab = bf.basis(m, 4)
+        cols = np.stack([bf.apply(m, st, stab, e.astype(np.complex128))[0] for e in np.eye(len(st))], 1)
+        assert np.abs(bf.dense_matrix(m, st) - cols).max() < 1e-13
+        fm = bf.FermionModel(8, c.perm, lat.characters(c, k), c.bonds, np.ones(8), np.full(8, 0.6))
+        fst, fstab = bf.fbasis(fm, 3)
+        fcols = np.stack([bf.fapply(fm, fst, fstab, e.astype(np.complex128))[0] for e in np.eye(len(fst))], 1)
+        assert np.abs(bf.fdense_matrix(fm, fst) - fcols).max() < 1e-13
