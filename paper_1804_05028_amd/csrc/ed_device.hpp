@@ -439,18 +439,16 @@ __device__ __forceinline__ uint64_t slot_of_state(uint64_t s, int log2n)
 }
 
 // first 16 bytes of a slot: {key, x} (real) or {key, -} (complex).  Slot
-// reads are random and rarely reused, so the real slots are read with
-// non-temporal loads, which keeps them from displacing the streamed basis and
-// vectors in the caches.  A complex slot is two 16-byte reads of one line:
-// with a non-temporal first read the line is often gone when the second
-// arrives (1.20 lines per term on the 36-site momentum sector, against 1.08
-// with ordinary loads), so both are ordinary loads.
+// reads are random and rarely reused, yet ordinary loads measure faster than
+// non-temporal ones: 2.4 % on the 40-site J1-J2 Gamma sector with real
+// slots.  A complex slot is two 16-byte reads of one line, and with a
+// non-temporal first read the line is often gone when the second arrives
+// (1.20 lines per term on the 36-site momentum sector, against 1.08).
 template <bool CPLX>
 __device__ __forceinline__ ulonglong2 load_slot(const char *slots, uint64_t sl)
 {
     typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
-    const u64x2 *p = (const u64x2 *)(slots + (sl << (CPLX ? 5 : 4)));
-    const u64x2 v = CPLX ? *p : __builtin_nontemporal_load(p);
+    const u64x2 v = *(const u64x2 *)(slots + (sl << (CPLX ? 5 : 4)));
     return make_ulonglong2(v.x, v.y);
 }
 

@@ -99,6 +99,33 @@ def test_index_and_table_variants(name, tuning):
         b.close()
 
 
+WAVES = [(th, sm) for th in (512, 1024) for sm in (1, 2)]
+
+
+@pytest.mark.parametrize("threads,search", WAVES, ids=[f"t{t}_s{s}" for t, s in WAVES])
+def test_every_wave_of_a_block_with_one_byte_single_chunk_tables(threads, search):
+    """Blocks of 8 and 16 waves over a 1321-row sector with 1-byte,
+    single-chunk action tables (the smallest LDS footprint): every row, on
+    repeated launches, against the oracle.  Rows 256 onwards are computed by
+    the second and later waves of each SIMD."""
+    ed = _ed()
+    w = wl.square_20_j1j2(n_sub=4)
+    m = bf.Model.from_workload(w)
+    st, stab = bf.basis(m, w.n_up)
+    x = vec.normal_vector(len(st), seed=9)
+    y_ref, _, _ = bf.apply(m, st, stab, x)
+    b = ed.Basis.from_workload(w, {"table_entry_bytes": 1, "search_mode": search, "block_threads": threads})
+    try:
+        info = b.info()
+        assert (info["table_entry_bytes"], info["chunk_bits"], info["search_mode"]) == (1, 5, search)
+        xd = torch.as_tensor(x).cuda()
+        for _ in range(3):
+            y = b.apply(w.J, xd).cpu().numpy()
+            assert np.abs(y - y_ref).max() <= RTOL * np.abs(y_ref).max()
+    finally:
+        b.close()
+
+
 @pytest.mark.parametrize("name", [n for n, _ in SMALL])
 def test_basis_bit_exact(built, name):
     w, b = built[name]
