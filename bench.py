@@ -44,9 +44,16 @@ BYTES_ROW_CPLX, BYTES_TERM_CPLX = 41.0, 25.0
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_05028_amd", "csrc", f)
                for f in ("ed_kernels.hip", "ed_device.hpp", "ed_internal.hpp")]
 MEASURED_TRAFFIC = {
-    # (workload, n_sublat, index, chunk_bits): (kernel sha256, fetch bytes, write bytes)
+    # (workload, n_sublat, index, chunk_bits): (kernel sha256, fetch bytes, write bytes, profile)
     ("square40_j1j2", 4, "hash-slot", 5): (
-        "cbbaaaec8104eb43d71753dc667cf74c7d6de096e0a6734731fe717853040e9c", 4.93176e+12, 3.44728e+09),
+        "bd77d164c1a7fb7a49b16fb1b90e3b5a42bf5bbdb2fd46d935965ad7226b831a", 4.72861e+12, 3.44728e+09,
+        "profiles/k_apply_square40_j1j2_ns4.md"),
+    ("triangular36_k1", 4, "hash-slot", 5): (
+        "bd77d164c1a7fb7a49b16fb1b90e3b5a42bf5bbdb2fd46d935965ad7226b831a", 1.94343e+12, 4.03337e+09,
+        "profiles/k_apply_triangular36_k1_complex.md"),
+    ("triangular36_tV", 4, "hash-slot", 3): (
+        "bd77d164c1a7fb7a49b16fb1b90e3b5a42bf5bbdb2fd46d935965ad7226b831a", 3.05797e+11, 3.36083e+08,
+        "profiles/k_apply_fermions_triangular36_tV.md"),
 }
 
 
@@ -55,12 +62,10 @@ MEASURED_TRAFFIC = {
 # time); not measured by this script.
 MEASURED_INT_OPS = {
     ("square40_j1j2", 4, "hash-slot", 5): {
-        "rate": 9.3e12, "unit": "lane-ops/s", "valu_issue_floor_frac": 0.57,
+        "rate": 9.53e12, "unit": "lane-ops/s", "valu_issue_floor_frac": 0.58,
         "source": "profiles/k_apply_square40_j1j2_ns4.md (rocprofv3 --pmc SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64), "
                   "not measured in this run"},
 }
-PROFILE_SOURCE = ("profiles/k_apply_square40_j1j2_ns4.md (rocprofv3 --pmc FETCH_SIZE, WRITE_SIZE, scaled by a "
-                  "plain copy), not measured in this run")
 
 
 def kernel_digest():
@@ -73,10 +78,11 @@ def kernel_digest():
 
 
 def measured_traffic(key):
+    """(fetch bytes, write bytes, profile) of the current kernel sources, or None."""
     rec = MEASURED_TRAFFIC.get(key)
-    if rec is None:
+    if rec is None or kernel_digest() != rec[0]:
         return None
-    return rec[1] + rec[2] if kernel_digest() == rec[0] else None
+    return rec[1], rec[2], rec[3]
 
 
 AUTOTUNE_NSUB = {"square40_j1j2": [4, 5], "square40_j1j2j3": [4, 5], "triangular36": [3, 4], "triangular36_k1": [4],
@@ -561,12 +567,14 @@ def main():
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     index_name = ["hash-slot", "limits"][info["index_mode"]]
     key = (args.workload, info["n_sublat"], index_name, info["chunk_bits"])
-    traffic = measured_traffic(key)
+    meas = measured_traffic(key)
+    traffic = meas[0] + meas[1] if meas else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "traffic_source": PROFILE_SOURCE if traffic else None,
+                "traffic_source": (f"{meas[2]} (rocprofv3 --pmc FETCH_SIZE, WRITE_SIZE, scaled by a plain copy), "
+                                   "not measured in this run") if meas else None,
                 "traffic_gbs": round(traffic / (kernel_ms * 1e-3) / 1e9, 1) if traffic else None,
-                "lines_per_term": round(traffic / 128.0 / kept, 3) if traffic and kept else None,
+                "lines_per_term": round(meas[0] / 128.0 / kept, 3) if meas and kept else None,
                 "kernel": "k_apply (fused H.v)", "alg_bytes_per_launch": alg_bytes,
                 "alg_bytes_per_unit": {"row": br, "kept_term": bt},
                 "launch_ms": round(kernel_ms, 3), "scatter_ms": round(pack_ms, 3),
