@@ -1237,10 +1237,18 @@ template <int MODE>
 static int apply_dispatch(const ed_basis *b, const void *x, void *y, const void *vprev, double *partials,
                           unsigned long long *stats, const LzState *lz, double jsq, hipStream_t st)
 {
-    if (b->fermion) {   // 4-byte tables, hash index, search loops read at run time
-        if (b->dm.is_complex)
-            return apply_impl<true, uint32_t, IDX_HASH, MODE, 0, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
-        return apply_impl<false, uint32_t, IDX_HASH, MODE, 0, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    if (b->fermion) {   // 4-byte tables, hash index, one-stage search
+        // four sublattices with two or three chunks: both counts fixed at
+        // compile time; other shapes read them at run time
+        const bool c = b->dm.is_complex;
+        if (b->dm.ns == 4 && b->dm.n_chunks == 3)
+            return c ? apply_impl<true, uint32_t, IDX_HASH, MODE, 35, true>(b, x, y, vprev, partials, stats, lz, jsq, st)
+                     : apply_impl<false, uint32_t, IDX_HASH, MODE, 35, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
+        if (b->dm.ns == 4 && b->dm.n_chunks == 2)
+            return c ? apply_impl<true, uint32_t, IDX_HASH, MODE, 34, true>(b, x, y, vprev, partials, stats, lz, jsq, st)
+                     : apply_impl<false, uint32_t, IDX_HASH, MODE, 34, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
+        return c ? apply_impl<true, uint32_t, IDX_HASH, MODE, 0, true>(b, x, y, vprev, partials, stats, lz, jsq, st)
+                 : apply_impl<false, uint32_t, IDX_HASH, MODE, 0, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
     }
     if (b->dm.act_bytes == 1) return apply_dispatch_t<MODE, uint8_t>(b, x, y, vprev, partials, stats, lz, jsq, st);
     if (b->dm.act_bytes == 2) return apply_dispatch_t<MODE, uint16_t>(b, x, y, vprev, partials, stats, lz, jsq, st);
