@@ -364,17 +364,22 @@ __device__ __forceinline__ uint64_t find_rep_staged(const Ctx<AT> &c, uint64_t s
 // pairs in two chunks of one block from the chunk images: for the chunks in
 // source order, the pairs an image forms with the images of the earlier
 // chunks that land below it.  Returns the parity (0 or 1); 4-byte entries.
-template <typename AT>
+template <typename AT, int NSC = 0>
 __device__ __forceinline__ uint32_t fermi_parity(const Ctx<AT> &c, uint32_t u, uint64_t s)
 {
     static_assert(sizeof(AT) == 4, "fermionic tables use 4-byte entries");
+    // sublattice and chunk counts fixed at compile time when NSC gives them
+    constexpr int NS_ = (NSC & 127) / 8, NC_ = NSC % 8;
+    const int ns = NS_ > 0 ? NS_ : c.ns, nc = NC_ > 0 ? NC_ : c.nc;
     uint32_t par = 0;
     uint64_t seen = 0;   // target blocks of the earlier source blocks with odd occupation
-    for (int X = 0; X < c.ns; ++X) {
+#pragma unroll
+    for (int X = 0; X < ns; ++X) {
         const uint32_t sx = (uint32_t)(s >> (c.N - (X + 1) * c.m)) & c.mmask;
-        const AT *t = c.act + ((size_t)(u * c.ns + X) * c.nc << c.cb);
+        const AT *t = c.act + ((size_t)(u * ns + X) * nc << c.cb);
         uint32_t earlier = 0, pos = 0;
-        for (int k = c.nc - 1; k >= 0; --k) {   // chunk nc-1 holds the block's first orbitals
+#pragma unroll
+        for (int k = nc - 1; k >= 0; --k) {   // chunk nc-1 holds the block's first orbitals
             const uint32_t e = t[(k << c.cb) | ((sx >> (k * c.cb)) & c.cmask)];
             const uint32_t img = e & 0xFFFFu;
             uint32_t px = earlier;               // px bit j: parity of earlier image bits at or below j

@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
             // fermions: hop sign times the Fermi sign of the element found
             auto fermi_amp = [&](int bi, uint64_t sp, uint32_t g, double jh) -> double {
                 if constexpr (FERMI) {
-                    const uint32_t par = ((uint32_t)__popcll(s & c.between[bi]) & 1u) ^ fermi_parity(c, c.g_u[g], sp);
+                    const uint32_t par = ((uint32_t)__popcll(s & c.between[bi]) & 1u) ^ fermi_parity<AT, NS>(c, c.g_u[g], sp);
                     return par ? -jh : jh;
                 }
                 return jh;
