@@ -112,7 +112,7 @@ def _workload(name, n_sub):
         return wl.square_4x4(n_sub=n_sub or 4), "Heisenberg square 16 (4x4), 16T, k=0, Sz=0"
     if name == "triangular36_tV":
         return (wl.triangular_36_tV(n_sub=n_sub or 4, V=1.0),
-                "spinless fermions t=1 V=1, triangular 36 (6,0)x(0,6), 18 particles, 36T x C6v, Gamma.A1")
+                "spinless fermions t=1 V=1, triangular 36 (6,0)x(0,6), 18 particles, 36T x C6, Gamma.A")
     raise SystemExit(f"unknown workload {name}")
 
 
