@@ -40,10 +40,11 @@ def test_several_gpus_are_refused():
 
 def test_traffic_is_reported_only_for_the_profiled_kernel():
     assert bench.measured_traffic(("no-such-workload", 4, "hash-slot", 5)) is None
-    key = next(iter(bench.MEASURED_TRAFFIC))
-    digest, fetch, write = bench.MEASURED_TRAFFIC[key]
-    t = bench.measured_traffic(key)
-    assert t is None or (bench.kernel_digest() == digest and t == fetch + write)
+    for key, (digest, fetch, write, profile) in bench.MEASURED_TRAFFIC.items():
+        t = bench.measured_traffic(key)
+        assert t is None or (bench.kernel_digest() == digest and t == (fetch, write, profile))
+        # every figure names a committed profile summary
+        assert os.path.exists(os.path.join(ROOT, profile)), profile
 
 
 def test_gamma_irreps_workload():
