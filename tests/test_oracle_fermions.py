@@ -90,11 +90,14 @@ def _free_pin(cluster, n_part, level):
     return dim == math.comb(n, n_part) and np.allclose(np.sort(evs), want, atol=1e-10)
 
 
-@pytest.mark.parametrize("level", ["formula", "definition"])
-@pytest.mark.parametrize("name,cluster,n_part", _free_cases(), ids=[f"{c[0]}_N{c[2]}" for c in _free_cases()])
-def test_free_fermion_spectra(name, cluster, n_part, level):
-    if level == "definition" and name == "sq16T":
-        pytest.skip("dense definition level kept to the smaller clusters")
+# the dense definition level is kept to the clusters of at most 12 orbitals
+FREE = [(lvl, c) for c in _free_cases() for lvl in ("formula", "definition")
+        if lvl == "formula" or c[1].n_sites <= 12]
+
+
+@pytest.mark.parametrize("level,case", FREE, ids=[f"{c[0]}_N{c[2]}-{lvl}" for lvl, c in FREE])
+def test_free_fermion_spectra(level, case):
+    name, cluster, n_part = case
     assert _free_pin(cluster, n_part, level)
 
 
