@@ -445,6 +445,24 @@ def cpu_baseline(w, rows, seed):
                        f"({kept + len(sample)} terms) by brute-force group application, {dt:.1f} s")
 
 
+PROBE_BYTES = 1 << 32       # 4 GiB: far beyond the 4 MB L2 of an XCD and the 256 MB MALL
+
+
+def random_read_probe(reps=5, iters=512):
+    """Independent random 16-byte reads per second over a 4 GiB device buffer
+    (ed_probe_random_reads): one 128 B line request each, the rate that bounds
+    the H.v gather's one slot read per term."""
+    import torch
+    from paper_1804_05028_amd import _lib as L
+    buf = torch.zeros(PROBE_BYTES, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    rate = L.ed_probe_random_reads(buf, PROBE_BYTES, iters, reps, torch.cuda.current_stream().cuda_stream)
+    del buf
+    torch.cuda.empty_cache()
+    return {"reads_per_s": rate, "read_bytes": 16, "buffer_bytes": PROBE_BYTES, "reps": reps,
+            "kernel": "ed_probe_random_reads (two 1024-thread blocks per CU, two reads in flight per lane)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -473,6 +491,8 @@ def main():
                     help="also time the adjoint (dL/dx = H gy and the per-bond sums) on the same basis")
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload: skip the batched Gamma-irrep, adjoint and small-oracle measurements")
+    ap.add_argument("--probe-only", action="store_true",
+                    help="run only the random-read probe (the ceiling of the H.v gather) and print its rate")
     ap.add_argument("--autotune", action="store_true",
                     help="search sublattice decompositions and launch tunings first, then bench the fastest")
     args = ap.parse_args()
@@ -488,6 +508,9 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs an MI355X GPU")
     torch.cuda.set_device(0)
+    if args.probe_only:
+        print(json.dumps(random_read_probe()))
+        return
     if args.workload in BATCHED_WORKLOADS:
         return bench_allk(args)
     w, desc = _workload(args.workload, args.n_sub)
@@ -583,6 +606,13 @@ def main():
 
     int_ops = MEASURED_INT_OPS.get(key) if traffic else None
     del x, y, res
+    probe = random_read_probe()
+    if meas:
+        # line requests the H.v kernel issues per second, against the probe's rate
+        kernel_lines = meas[0] / 128.0 / (kernel_ms * 1e-3)
+        probe["kernel_line_requests_per_s"] = round(kernel_lines, 1)
+        probe["kernel_frac_of_probe"] = round(kernel_lines / probe["reads_per_s"], 4)
+    roofline["random_read_ceiling"] = probe
     basis.close()
     torch.cuda.empty_cache()
 

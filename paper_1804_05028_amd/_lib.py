@@ -110,6 +110,7 @@ PROTOTYPES = {
     "ed_apply_H": (ctypes.c_int, [P, P, P, P, P]),
     "ed_apply_H_stats": (ctypes.c_int, [P, P, P, P, P]),
     "ed_apply_H_timed": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P]),
+    "ed_probe_random_reads": (ctypes.c_int, [P, ctypes.c_int64, I32, I32, P, P]),
     "ed_build_basis_fermions": (ctypes.c_int, [P, P, P, I32, P, P, P]),
     "ed_apply_H_fermions": (ctypes.c_int, [P, P, P, P, P, P]),
     "ed_lanczos_fermions": (ctypes.c_int, [P, P, P, P, I32, P, P, P, P, P]),
@@ -338,6 +339,13 @@ def ed_apply_H_timed(h, J, Jz, x_dev, y_dev, reps, stream=None):
     check(lib().ed_apply_H_timed(h, J.ctypes.data, None if Jz is None else Jz.ctypes.data, ptr(x_dev), ptr(y_dev),
                                  int(reps), ctypes.byref(pack), ctypes.byref(kern), stream))
     return pack.value, kern.value
+
+
+def ed_probe_random_reads(buf_dev, nbytes, iters=512, reps=3, stream=None):
+    """Independent random 16-byte reads per second over a device buffer."""
+    rate = ctypes.c_double()
+    check(lib().ed_probe_random_reads(ptr(buf_dev), int(nbytes), int(iters), int(reps), ctypes.byref(rate), stream))
+    return rate.value
 
 
 def ed_apply_H_fermions(h, t, V, x_dev, y_dev, stream=None):

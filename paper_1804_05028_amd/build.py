@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libed.so")
-SOURCES = ["ed_kernels.hip", "ed_multi.hip", "ed_tables.cpp", "ed_api.cpp"]
+SOURCES = ["ed_kernels.hip", "ed_multi.hip", "ed_probe.hip", "ed_tables.cpp", "ed_api.cpp"]
 ARCH = "gfx950"
 
 

@@ -272,3 +272,16 @@ def test_tuning_modes_are_validated_before_any_device_work():
     _expect("ED_ERR_ARG", lambda: L.ed_build_basis(arrays, w.n_up, {"search_mode": -1}))
     _expect("ED_ERR_ARG", lambda: L.ed_build_basis(arrays, w.n_up, {"lanes_per_row": 3}))
     _expect("ED_ERR_ARG", lambda: L.ed_build_basis(arrays, w.n_up, {"lanczos_direct": 2}))
+
+
+def test_random_read_probe_rejects_bad_arguments_before_any_device_work():
+    """ed_probe_random_reads checks its sizes on the host (no GPU needed)."""
+    fake = 0x1000   # never dereferenced: every call below fails its argument checks first
+    for nbytes, iters, reps in ((3 << 20, 512, 1), (1 << 19, 512, 1), (1 << 30, 511, 1), (1 << 30, 0, 1),
+                                (1 << 30, 8192, 1), (1 << 30, 512, 0), (1 << 30, 512, 101)):
+        with pytest.raises(L.EDError) as e:
+            L.ed_probe_random_reads(fake, nbytes, iters, reps)
+        assert e.value.name == "ED_ERR_ARG", (nbytes, iters, reps)
+    with pytest.raises(L.EDError) as e:
+        L.ed_probe_random_reads(None, 1 << 30, 512, 1)
+    assert e.value.name == "ED_ERR_ARG"
