@@ -448,19 +448,22 @@ def cpu_baseline(w, rows, seed):
 PROBE_BYTES = 1 << 32       # 4 GiB: far beyond the 4 MB L2 of an XCD and the 256 MB MALL
 
 
-def random_read_probe(reps=5, iters=512):
-    """Independent random 16-byte reads per second over a 4 GiB device buffer
-    (ed_probe_random_reads): one 128 B line request each, the rate that bounds
-    the H.v gather's one slot read per term."""
+def random_read_probe(reps=5, iters=512, slot_bytes=16):
+    """Independent random slot reads per second over a 4 GiB device buffer
+    (ed_probe_random_reads): 16-byte slots as real sectors read them, or
+    32-byte slots read as two 16-byte loads as complex sectors do.  One 128 B
+    line request per slot: the rate that bounds the H.v gather's one slot
+    read per term."""
     import torch
     from paper_1804_05028_amd import _lib as L
     buf = torch.zeros(PROBE_BYTES, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
-    rate = L.ed_probe_random_reads(buf, PROBE_BYTES, iters, reps, torch.cuda.current_stream().cuda_stream)
+    rate = L.ed_probe_random_reads(buf, PROBE_BYTES, iters, reps, torch.cuda.current_stream().cuda_stream,
+                                   slot_bytes=slot_bytes)
     del buf
     torch.cuda.empty_cache()
-    return {"reads_per_s": rate, "read_bytes": 16, "buffer_bytes": PROBE_BYTES, "reps": reps,
-            "kernel": "ed_probe_random_reads (two 1024-thread blocks per CU, two reads in flight per lane)"}
+    return {"reads_per_s": rate, "slot_bytes": slot_bytes, "buffer_bytes": PROBE_BYTES, "reps": reps,
+            "kernel": "ed_probe_random_reads (two 1024-thread blocks per CU, two slots in flight per lane)"}
 
 
 def main():
@@ -509,7 +512,7 @@ def main():
         raise SystemExit("bench.py needs an MI355X GPU")
     torch.cuda.set_device(0)
     if args.probe_only:
-        print(json.dumps(random_read_probe()))
+        print(json.dumps([random_read_probe(slot_bytes=16), random_read_probe(slot_bytes=32)]))
         return
     if args.workload in BATCHED_WORKLOADS:
         return bench_allk(args)
@@ -606,7 +609,7 @@ def main():
 
     int_ops = MEASURED_INT_OPS.get(key) if traffic else None
     del x, y, res
-    probe = random_read_probe()
+    probe = random_read_probe(slot_bytes=32 if cplx else 16)
     if meas:
         # line requests the H.v kernel issues per second, against the probe's rate
         kernel_lines = meas[0] / 128.0 / (kernel_ms * 1e-3)

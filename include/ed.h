@@ -249,16 +249,18 @@ int ed_apply_H_timed(const ed_basis_t *b, const double *J, const double *Jz, con
  * Random-read probe, the ceiling the H.v gather is measured against: the
  * gather form of the sector H.v (sec. "Parallel matrix-vector multiplication")
  * reads one target slot per off-diagonal term at an unrelated address.  The
- * probe reads 16-byte words at pseudo-random 16-byte-aligned offsets of
- * buf_dev (device memory of `bytes` bytes, a power of two >= 1 MiB, owned by
- * the caller, contents irrelevant), iters (even, 2..4096) reads per lane with
- * two in flight, two 1024-thread blocks per compute unit; one untimed launch,
- * then reps (1..100) timed ones on stream.  *reads_per_s receives the mean
- * rate.  Writes nothing to buf_dev; allocates nothing.  Synchronises.
- * ED_ERR_ARG on bad sizes or null pointers.
+ * probe reads slots of slot_bytes (16: one 16-byte load, as real sectors do;
+ * 32: two 16-byte loads of one 32-byte slot, as complex sectors do) at
+ * pseudo-random slot-aligned offsets of buf_dev (device memory of `bytes`
+ * bytes, a power of two >= 1 MiB, owned by the caller, contents irrelevant),
+ * iters (even, 2..4096) slots per lane with two in flight, two 1024-thread
+ * blocks per compute unit; one untimed launch, then reps (1..100) timed ones
+ * on stream.  *reads_per_s receives the mean rate in slots per second.
+ * Writes nothing to buf_dev; allocates nothing.  Synchronises.  ED_ERR_ARG
+ * on bad sizes or null pointers.
  */
-int ed_probe_random_reads(const void *buf_dev, int64_t bytes, int32_t iters, int32_t reps, double *reads_per_s,
-                          void *stream);
+int ed_probe_random_reads(const void *buf_dev, int64_t bytes, int32_t slot_bytes, int32_t iters, int32_t reps,
+                          double *reads_per_s, void *stream);
 
 /*
  * XXZ form of ed_apply_H: each bond contributes the exchange

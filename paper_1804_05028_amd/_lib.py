@@ -110,7 +110,7 @@ PROTOTYPES = {
     "ed_apply_H": (ctypes.c_int, [P, P, P, P, P]),
     "ed_apply_H_stats": (ctypes.c_int, [P, P, P, P, P]),
     "ed_apply_H_timed": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P]),
-    "ed_probe_random_reads": (ctypes.c_int, [P, ctypes.c_int64, I32, I32, P, P]),
+    "ed_probe_random_reads": (ctypes.c_int, [P, ctypes.c_int64, I32, I32, I32, P, P]),
     "ed_build_basis_fermions": (ctypes.c_int, [P, P, P, I32, P, P, P]),
     "ed_apply_H_fermions": (ctypes.c_int, [P, P, P, P, P, P]),
     "ed_lanczos_fermions": (ctypes.c_int, [P, P, P, P, I32, P, P, P, P, P]),
@@ -341,10 +341,12 @@ def ed_apply_H_timed(h, J, Jz, x_dev, y_dev, reps, stream=None):
     return pack.value, kern.value
 
 
-def ed_probe_random_reads(buf_dev, nbytes, iters=512, reps=3, stream=None):
-    """Independent random 16-byte reads per second over a device buffer."""
+def ed_probe_random_reads(buf_dev, nbytes, iters=512, reps=3, stream=None, slot_bytes=16):
+    """Independent random slot reads (16 or 32 bytes each) per second over a
+    device buffer."""
     rate = ctypes.c_double()
-    check(lib().ed_probe_random_reads(ptr(buf_dev), int(nbytes), int(iters), int(reps), ctypes.byref(rate), stream))
+    check(lib().ed_probe_random_reads(ptr(buf_dev), int(nbytes), int(slot_bytes), int(iters), int(reps),
+                                      ctypes.byref(rate), stream))
     return rate.value
 
 

@@ -29,20 +29,29 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-// every lane reads iters 16-byte words at pseudo-random 16-byte-aligned
-// offsets below (mask + 1) * 16, two reads in flight
+// every lane reads iters slots of 16 B (W = 1) or 32 B (W = 2, two 16-byte
+// loads of one 32-byte slot, as the complex H.v reads its slots) at
+// pseudo-random slot-aligned offsets below (mask + 1) * 16 * W, two slots in
+// flight
+template <int W>
 __global__ void __launch_bounds__(1024) k_probe_random_reads(const char *__restrict__ buf, uint64_t mask, int iters)
 {
     typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    constexpr int kShift = W == 2 ? 5 : 4;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t h = splitmix64(tid * 0x100000001b3ull + 1u);
     uint64_t acc = 0;
     for (int it = 0; it < iters; it += 2) {
         const uint64_t a = splitmix64(h + (uint64_t)it) & mask;
         const uint64_t b = splitmix64(h + (uint64_t)it + 1u) & mask;
-        const u64x2 va = *(const u64x2 *)(buf + (a << 4));
-        const u64x2 vb = *(const u64x2 *)(buf + (b << 4));
+        const u64x2 va = *(const u64x2 *)(buf + (a << kShift));
+        const u64x2 vb = *(const u64x2 *)(buf + (b << kShift));
         acc ^= va.x ^ va.y ^ vb.x ^ vb.y;
+        if constexpr (W == 2) {
+            const u64x2 wa = *(const u64x2 *)(buf + (a << kShift) + 16);
+            const u64x2 wb = *(const u64x2 *)(buf + (b << kShift) + 16);
+            acc ^= wa.x ^ wa.y ^ wb.x ^ wb.y;
+        }
     }
     if (acc == 0x5bd1e9955bd1e995ull) g_probe_sink = acc;
 }
@@ -51,11 +60,12 @@ __global__ void __launch_bounds__(1024) k_probe_random_reads(const char *__restr
 
 }  // namespace ed
 
-extern "C" int ed_probe_random_reads(const void *buf_dev, int64_t bytes, int32_t iters, int32_t reps,
-                                     double *reads_per_s, void *stream)
+extern "C" int ed_probe_random_reads(const void *buf_dev, int64_t bytes, int32_t slot_bytes, int32_t iters,
+                                     int32_t reps, double *reads_per_s, void *stream)
 {
     using namespace ed;
     if (!buf_dev || !reads_per_s) return set_error(ED_ERR_ARG, "null argument");
+    if (slot_bytes != 16 && slot_bytes != 32) return set_error(ED_ERR_ARG, "slot_bytes = %d (16 or 32)", slot_bytes);
     if (bytes < (1 << 20) || (bytes & (bytes - 1))) return set_error(ED_ERR_ARG, "bytes = %lld (a power of two, >= 1 MiB)", (long long)bytes);
     if (iters < 2 || iters > 4096 || (iters & 1)) return set_error(ED_ERR_ARG, "iters = %d (even, 2..4096)", iters);
     if (reps < 1 || reps > 100) return set_error(ED_ERR_ARG, "reps = %d (1..100)", reps);
@@ -65,7 +75,8 @@ extern "C" int ed_probe_random_reads(const void *buf_dev, int64_t bytes, int32_t
         n_cu <= 0)
         return set_error(ED_ERR_HIP, "device query failed");
     const int threads = 1024, blocks = 2 * n_cu;   // two 1024-thread blocks per compute unit
-    const uint64_t mask = (uint64_t)(bytes >> 4) - 1u;
+    const uint64_t mask = (uint64_t)(bytes / slot_bytes) - 1u;
+    auto kern = slot_bytes == 32 ? k_probe_random_reads<2> : k_probe_random_reads<1>;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);
@@ -73,10 +84,10 @@ extern "C" int ed_probe_random_reads(const void *buf_dev, int64_t bytes, int32_t
     }
     int rc = ED_OK;
     // one untimed launch, then reps timed ones
-    hipLaunchKernelGGL(k_probe_random_reads, dim3(blocks), dim3(threads), 0, st, (const char *)buf_dev, mask, iters);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, st, (const char *)buf_dev, mask, iters);
     if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(ED_ERR_HIP, "event record failed");
     for (int r = 0; r < reps && rc == ED_OK; ++r)
-        hipLaunchKernelGGL(k_probe_random_reads, dim3(blocks), dim3(threads), 0, st, (const char *)buf_dev, mask, iters);
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, st, (const char *)buf_dev, mask, iters);
     if (rc == ED_OK && hipGetLastError() != hipSuccess) rc = set_error(ED_ERR_HIP, "probe launch failed");
     if (rc == ED_OK && hipEventRecord(e1, st) != hipSuccess) rc = set_error(ED_ERR_HIP, "event record failed");
     if (rc == ED_OK && hipEventSynchronize(e1) != hipSuccess)

@@ -285,3 +285,7 @@ def test_random_read_probe_rejects_bad_arguments_before_any_device_work():
     with pytest.raises(L.EDError) as e:
         L.ed_probe_random_reads(None, 1 << 30, 512, 1)
     assert e.value.name == "ED_ERR_ARG"
+    for sb in (0, 8, 24, 64):
+        with pytest.raises(L.EDError) as e:
+            L.ed_probe_random_reads(fake, 1 << 30, 512, 1, slot_bytes=sb)
+        assert e.value.name == "ED_ERR_ARG", sb
