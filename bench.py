@@ -327,7 +327,10 @@ def time_adjoint(basis, J, x, reps, hv_ms):
     print(f"[bench] adjoint {full_ms:.2f} ms (per-bond sums {gj_ms:.2f} ms, H.v {hv_ms:.2f} ms)", file=sys.stderr,
           flush=True)
     return {"backward_ms": full_ms, "per_bond_sums_ms": gj_ms, "hv_ms": hv_ms, "backward_over_hv": full_ms / hv_ms,
-            "n_bonds": int(basis.n_bonds)}
+            "n_bonds": int(basis.n_bonds),
+            "path": ("one fused pass for gx and the per-bond sums (real sector, hash slots; its 32-byte adjoint "
+                     "slot table allocated by the untimed first call)") if not basis.is_complex
+            else "H gy and the per-bond sums as two passes"}
 
 
 def vec_seed_target():

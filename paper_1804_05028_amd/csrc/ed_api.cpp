@@ -422,13 +422,17 @@ static int backward_common(const ed_basis_t *b, const double *J, const void *x_d
     if (!b) return set_error(ED_ERR_ARG, "null basis");
     if (b->fermion) return set_error(ED_ERR_UNSUPPORTED, "the adjoint covers spin bases");
     if (b->db.dim > 0 && !gy_dev) return set_error(ED_ERR_ARG, "null gy");
+    if (gx_dev && gx_dev == gy_dev) return set_error(ED_ERR_ARG, "gx and gy must be distinct");
+    if (gJ_host && b->db.dim > 0 && !x_dev) return set_error(ED_ERR_ARG, "null x");
+    if (gx_dev && gJ_host && gx_dev == x_dev) return set_error(ED_ERR_ARG, "gx and x must be distinct");
+    // both products of a real sector in one pass (one search and one slot line per term)
+    if (gx_dev && gJ_host && !static_scratch && ed::backward_fusable(b))
+        return ed::launch_backward_J(b, J, x_dev, gy_dev, gJ_host, stream, false, gx_dev);
     if (gx_dev) {
-        if (gx_dev == gy_dev) return set_error(ED_ERR_ARG, "gx and gy must be distinct");
         int rc = ed::launch_apply(b, J, nullptr, gy_dev, gx_dev, stream, 0, nullptr);
         if (rc) return rc;
     }
     if (gJ_host) {
-        if (b->db.dim > 0 && !x_dev) return set_error(ED_ERR_ARG, "null x");
         int rc = ed::launch_backward_J(b, J, x_dev, gy_dev, gJ_host, stream, static_scratch);
         if (rc) return rc;
     }

@@ -225,17 +225,67 @@ __global__ void k_pack_cplx(const double2 *x, const uint32_t *slot_of, char *slo
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint slots: 32-byte {key, x, gy, -} at the positions of the 16-byte H.v
+// slots of a real sector (same keys, same probe sequences).
+// ---------------------------------------------------------------------------
+
+__global__ void k_adj_slots_keys(const char *slots, char *adj, uint64_t n_slots)
+{
+    for (uint64_t sl = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < n_slots;
+         sl += (uint64_t)gridDim.x * blockDim.x)
+        *(uint64_t *)(adj + (sl << 5)) = *(const uint64_t *)(slots + (sl << 4));
+}
+
+__global__ void k_pack_adj(const double *x, const double *gy, const uint32_t *slot_of, char *adj, int64_t D)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < D; j += (int64_t)gridDim.x * blockDim.x) {
+        char *p = adj + ((size_t)slot_of[j] << 5);
+        *(double *)(p + 8) = x[j];
+        *(double *)(p + 16) = gy[j];
+    }
+}
+
+// probe the adjoint slots from the home slot of target: both 16-byte halves
+// of a slot are requested together; returns 1 with the packed key, x and gy
+__device__ __forceinline__ int resolve_adj(const DevBasis &db, const char *adj, uint64_t sl, uint64_t target,
+                                           uint64_t &key, double &xv, double &gv)
+{
+    typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    const uint64_t smask = (1ull << db.slot_log2) - 1ull;
+    while (true) {
+        const u64x2 q = *(const u64x2 *)(adj + (sl << 5));
+        const u64x2 q2 = *(const u64x2 *)(adj + (sl << 5) + 16);
+        if (q.x == kEmpty) return 0;
+        if ((q.x & kStateMask) == target) {
+            key = q.x;
+            xv = __longlong_as_double((long long)q.y);
+            gv = __longlong_as_double((long long)q2.x);
+            return 1;
+        }
+        sl = (sl + 1) & smask;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint, bond part: A_b = Re sum_i conj(gy_i) (dH/dJ_b x)_i.  Bonds are
 // visited in the same order by every lane so that each bond's contributions
 // are summed across the wave in a fixed tree order, then across waves and
 // blocks in fixed order: the result is deterministic.
 // ---------------------------------------------------------------------------
 
-template <bool CPLX, typename AT, int INDEX, int NSC>
+// FUSED (real sectors, hash-slot index): the same pass also computes
+// gx = H gy.  Each target's x_j and gy_j come from one 32-byte slot
+// {key, x, gy, -} of adj, so one search and one line serve both products;
+// gx_i sums its terms in the order and form of k_apply, so it equals
+// ed_apply_H's H gy bit for bit.
+template <bool CPLX, typename AT, int INDEX, int NSC, bool FUSED = false>
 __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, const typename Scalar<CPLX>::T *__restrict__ x,
                                                      const typename Scalar<CPLX>::T *__restrict__ gy,
-                                                     double *partials /* [grid][nb + 1] */)
+                                                     double *partials /* [grid][nb + 1] */,
+                                                     const char *__restrict__ adj = nullptr, double *__restrict__ gx = nullptr,
+                                                     double jsum_quarter = 0.0)
 {
+    static_assert(!FUSED || (!CPLX && INDEX == IDX_HASH), "the fused adjoint covers real sectors with hash slots");
     // A_b = 1/4 sum_i Re(conj(gy_i) x_i)                      (every bond parallel)
     //     + sum_{i: b antiparallel} [ -1/2 Re(conj(gy_i) x_i) + Re(conj(gy_i) t_b(i)) ]
     // where t_b(i) is the flip term of bond b in row i.  Column nb of the
@@ -271,13 +321,35 @@ __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, c
             }
         }
         tot += wave_sum(gx_r);
+        double anti_sum = 0.0, ar = 0.0;   // FUSED: diagonal and off-diagonal parts of (H gy)_i
         for (int b = 0; b < nb; ++b) {
             const BondLds bd = c.bonds[b];
             const uint64_t t = s & bd.mask;
             const bool anti = valid && (t != 0) && (t != bd.mask);
             if (!__ballot(anti)) continue;   // no row of this wave flips bond b
             double contrib = 0.0;
-            if (anti) {
+            if (anti && FUSED) {
+                contrib = -0.5 * gx_r;
+                anti_sum += bd.jzhalf;
+                uint32_t g;
+                const uint64_t r = rep_search<AT, NSC>(c, s ^ bd.mask, g);
+                uint64_t key;
+                double xj, gj;
+                if (resolve_adj(db, adj, slot_of_state(r, db.slot_log2), r, key, xj, gj)) {
+                    double cr, ci;
+                    chi_of<false>(c, g, cr, ci);
+                    const double sq = c.div_sqrt[key >> kNormShift];
+                    // the per-bond term exactly as the unfused branch forms it
+                    const double vr = xj, vi = 0.0;
+                    const double amp = 0.5 * sq * rs_i;
+                    const double tr = amp * (cr * vr - ci * vi), ti = amp * (cr * vi + ci * vr);
+                    contrib += g_r * tr + g_i * ti;
+                    // and the H gy term exactly as k_apply forms it
+                    const double wr = gj, wi = 0.0;
+                    const double ampg = bd.jhalf * rs_i * c.div_sqrt[key >> kNormShift];
+                    ar += ampg * (cr * wr - ci * wi);
+                }
+            } else if (anti) {
                 contrib = -0.5 * gx_r;
                 uint32_t g, mval = 0;
                 uint64_t r;
@@ -326,6 +398,7 @@ __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, c
                 else a3 += wsum;
             }
         }
+        if (FUSED && valid) gx[i] = (jsum_quarter - anti_sum) * g_r + ar;
     }
     // block reduction in fixed order (the tables are no longer needed)
     __syncthreads();
@@ -1358,12 +1431,12 @@ static int scratch_on_device(double **out)
 
 // per-bond adjoint sums; the partial sums live in scratch_dev when it is
 // given (at most kScratchDoubles doubles), else in buffers allocated here
-template <bool CPLX, typename AT, int INDEX, int NSC>
+template <bool CPLX, typename AT, int INDEX, int NSC, bool FUSED = false>
 static int backward_impl(const ed_basis *b, const void *x, const void *gy, double *gJ_host, double *scratch_dev,
-                         hipStream_t st)
+                         hipStream_t st, void *gx = nullptr, double jsq = 0.0)
 {
     using T = typename Scalar<CPLX>::T;
-    auto kern = k_backward_J<CPLX, AT, INDEX, NSC>;
+    auto kern = k_backward_J<CPLX, AT, INDEX, NSC, FUSED>;
     const int nb = b->t.nb;
     int grid, threads;
     launch_cfg(b, kern, b->dm.lds_total, &grid, &threads);
@@ -1385,7 +1458,8 @@ static int backward_impl(const ed_basis *b, const void *x, const void *gy, doubl
     }
     // every block writes its whole row of partials and every column sum is
     // written, so nothing has to start at zero
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, b->dm, b->db, (const T *)x, (const T *)gy, partials);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, b->dm, b->db, (const T *)x, (const T *)gy, partials,
+                       (const char *)b->adj_slots, (double *)gx, jsq);
     hipLaunchKernelGGL(k_sum_partials_cols, dim3((nb + 256) / 256), dim3(256), 0, st, (const double *)partials, grid,
                        nb + 1, out);
     double h[kMaxBondWords * 64 + 1];
@@ -1401,17 +1475,47 @@ static int backward_impl(const ed_basis *b, const void *x, const void *gy, doubl
     return ED_OK;
 }
 
+bool backward_fusable(const ed_basis *b)
+{
+    return !b->dm.is_complex && b->db.index_mode == IDX_HASH && !b->fermion;
+}
+
+// 32-byte adjoint slots of a real sector, made once per basis: keys copied
+// from the H.v slots
+static int ensure_adj_slots(const ed_basis *bc, hipStream_t st)
+{
+    ed_basis *b = const_cast<ed_basis *>(bc);
+    if (b->adj_slots) return ED_OK;
+    void *p = nullptr;
+    int rc = device_alloc(b, &p, (size_t)b->n_slots * 32);
+    if (rc) return rc;
+    const uint64_t n = (uint64_t)b->n_slots;
+    hipLaunchKernelGGL(k_adj_slots_keys, dim3((unsigned)std::min<uint64_t>((n + 255) / 256, 1u << 20)), dim3(256), 0, st,
+                       (const char *)b->db.slots, (char *)p, n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(ED_ERR_HIP, "adjoint slot setup failed: %s", hipGetErrorString(e));
+    b->adj_slots = (char *)p;
+    return ED_OK;
+}
+
 int launch_backward_J(const ed_basis *b, const double *J, const void *x, const void *gy, double *gJ_host, void *stream,
-                      bool static_scratch)
+                      bool static_scratch, void *gx)
 {
     hipStream_t st = (hipStream_t)stream;
+    if (gx && (static_scratch || !backward_fusable(b))) return set_error(ED_ERR_ARG, "no fused adjoint for this basis");
     int rc = check_couplings(b, J);
     if (rc) return rc;
     double jsq;
     rc = upload_couplings(b, J, nullptr, st, &jsq);
     if (rc) return rc;
-    if (b->db.dim == 0 || b->t.nb == 0) {
+    if (b->db.dim == 0) {
         for (int k = 0; k < b->t.nb; ++k) gJ_host[k] = 0.0;
+        return ED_OK;
+    }
+    if (b->t.nb == 0) {
+        for (int k = 0; k < b->t.nb; ++k) gJ_host[k] = 0.0;
+        // no bonds: H gy is the constant diagonal
+        if (gx) return launch_apply(b, J, nullptr, gy, gx, stream, 0, nullptr);
         return ED_OK;
     }
     double *scratch_dev = nullptr;
@@ -1419,12 +1523,31 @@ int launch_backward_J(const ed_basis *b, const double *J, const void *x, const v
         rc = scratch_on_device(&scratch_dev);
         if (rc) return rc;
     }
-    rc = pack_input(b, x, st);
-    if (rc) return rc;
     const bool c = b->dm.is_complex;
     const int ix = b->db.index_mode, w = b->dm.act_bytes;
     // four sublattices with one to three chunks: search loops fixed at compile time
     const int nsc = (ix == IDX_HASH && b->dm.ns == 4 && b->dm.n_chunks <= 3) ? 32 + b->dm.n_chunks : 0;
+    if (gx) {
+        // x and gy scattered into the 32-byte adjoint slots; one pass for gJ and gx
+        rc = ensure_adj_slots(b, st);
+        if (rc) return rc;
+        const int64_t D = b->db.dim;
+        hipLaunchKernelGGL(k_pack_adj, dim3((unsigned)std::min<int64_t>((D + 255) / 256, 1 << 20)), dim3(256), 0, st,
+                           (const double *)x, (const double *)gy, b->db.slot_of, b->adj_slots, D);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return set_error(ED_ERR_HIP, "adjoint pack failed: %s", hipGetErrorString(e));
+#define ED_FCASE(A, K) \
+    if (w == (int)sizeof(A) && nsc == K) return backward_impl<false, A, IDX_HASH, K, true>(b, x, gy, gJ_host, nullptr, st, gx, jsq);
+#define ED_FCASES(A) ED_FCASE(A, 0) ED_FCASE(A, 33) ED_FCASE(A, 34) ED_FCASE(A, 35)
+        ED_FCASES(uint8_t)
+        ED_FCASES(uint16_t)
+        ED_FCASES(uint32_t)
+#undef ED_FCASES
+#undef ED_FCASE
+        return set_error(ED_ERR_ARG, "no kernel variant");
+    }
+    rc = pack_input(b, x, st);
+    if (rc) return rc;
 #define ED_CASE(C, A, I, K) \
     if (c == C && w == (int)sizeof(A) && ix == I && nsc == K) \
         return backward_impl<C, A, I, K>(b, x, gy, gJ_host, scratch_dev, st);
