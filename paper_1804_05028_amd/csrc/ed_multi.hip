@@ -150,7 +150,7 @@ __global__ void __launch_bounds__((multi_block_bound<KB, SPLIT>()))
     const int lane = threadIdx.x & (kWave - 1);
     // the two-stage search is compiled in where registers allow it without
     // spilling; elsewhere the one-stage search gives the same results
-    constexpr bool kStagedFits = KB <= 4 || (SPLIT > 1 && KB <= 8);
+    constexpr bool kStagedFits = KB <= 8;
     // the same instances can read a character table kept in HBM
     constexpr bool kChiHbm = kStagedFits;
     // this lane's row within the wave's group of rows, and its sectors
@@ -357,20 +357,37 @@ __global__ void __launch_bounds__(kMlzThreads) k_mlz_init_norm(const double2 *v0
         partials);
 }
 
-// sum the per-block partials of every sector in block order
-__device__ __forceinline__ double sector_total(const double *partials, int nblk, int K, int k)
+// Per-sector totals of the per-block partials, by every thread of a block
+// of kTotThreads: the G = kTotThreads / K threads of sector k each add the
+// blocks r, r + G, ... in order, and thread k then adds their G sums in
+// order, so the result is deterministic.  Every thread must call it; the
+// totals are valid in threads k < K.
+constexpr int kTotThreads = 1024;
+__device__ __forceinline__ double sector_total(const double *partials, int nblk, int K)
 {
+    __shared__ double red[kTotThreads];
+    const int t = threadIdx.x;
+    const int G = kTotThreads / K;
+    const int k = t % K, r = t / K;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partials[(size_t)b * K + k];
-    return s;
+    if (r < G)
+        for (int b = r; b < nblk; b += G) s += partials[(size_t)b * K + k];
+    red[t] = s;
+    __syncthreads();
+    double tot = 0.0;
+    if (t < K)
+        for (int q = 0; q < G; ++q) tot += red[q * K + t];
+    __syncthreads();
+    return tot;
 }
 
-__global__ void k_mlz_init_finish(const double *partials, int nblk, int K, MlzSector *sec, MlzState *st)
+__global__ void __launch_bounds__(kTotThreads) k_mlz_init_finish(const double *partials, int nblk, int K, MlzSector *sec,
+                                                                  MlzState *st)
 {
     const int k = threadIdx.x;
     int active = 0;
+    const double n2 = sector_total(partials, nblk, K);
     if (k < K) {
-        const double n2 = sector_total(partials, nblk, K, k);
         MlzSector s{};
         s.done = n2 > 0.0 ? 0 : 1;   // empty sector or zero start vector: nothing to iterate
         s.inv_beta = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
@@ -411,12 +428,12 @@ __global__ void __launch_bounds__(kMlzThreads) k_mlz_dot(const double2 *v, const
         partials);
 }
 
-__global__ void k_mlz_alpha(const double *partials, int nblk, int K, MlzSector *sec, const MlzState *st,
-                            double *ahist, int n_steps)
+__global__ void __launch_bounds__(kTotThreads) k_mlz_alpha(const double *partials, int nblk, int K, MlzSector *sec,
+                                                            const MlzState *st, double *ahist, int n_steps)
 {
     const int k = threadIdx.x;
+    const double a = sector_total(partials, nblk, K);
     if (k >= K) return;
-    const double a = sector_total(partials, nblk, K, k);
     sec[k].alpha = a;
     if (!sec[k].done) ahist[(size_t)k * n_steps + st->j] = a;
 }
@@ -440,15 +457,16 @@ __global__ void __launch_bounds__(kMlzThreads) k_mlz_update(double2 *w, const do
         partials);
 }
 
-__global__ void k_mlz_beta(const double *partials, int nblk, int K, MlzSector *sec, MlzState *st, double *bhist,
-                           int n_steps, double tol)
+__global__ void __launch_bounds__(kTotThreads) k_mlz_beta(const double *partials, int nblk, int K, MlzSector *sec,
+                                                           MlzState *st, double *bhist, int n_steps, double tol)
 {
     const int k = threadIdx.x;
     const int j = st->j;
     int active = 0;
+    const double n2 = sector_total(partials, nblk, K);
     if (k < K) {
         MlzSector s = sec[k];
-        const double b = sqrt(sector_total(partials, nblk, K, k));
+        const double b = sqrt(n2);
         if (!s.done) {
             s.scale = fmax(s.scale, fmax(fabs(s.alpha), b));
             bhist[(size_t)k * n_steps + j] = b;
@@ -519,16 +537,19 @@ static int multi_launch_impl(const ed_multi *mb, const void *x, void *y, const v
 // lanes per row of the batched H.v: the caller's choice, else 1 lane for up
 // to 2 sectors, 2 lanes for up to 8 and 4 lanes above (measured on the
 // 36-site triangular momentum sectors: each lane then holds at most 4
-// sectors for K <= 16 and prefetches their next amplitudes); raised where
-// the character table lives in HBM (see kChiHbm)
+// sectors for K <= 16 and prefetches their next amplitudes).  With the
+// character table in HBM, 1 lane for up to 8 sectors (measured on the 8
+// Gamma irreps of the 36-site triangular group, whose search dominates:
+// 47.2 ms against 51.6 ms with 2 lanes); such a table needs an instance
+// with the HBM path (see kChiHbm), at most 8 sectors per lane.
 int multi_lanes_per_row(const ed_multi *mb)
 {
     const int K = mb->K;
     int t = mb->base->tuning.lanes_per_row;
-    if (t <= 0) t = K <= 2 ? 1 : (K <= 8 ? 2 : 4);
-    // a character table read from HBM needs an instance with at most 4
-    // sectors per lane, or 8 per lane on a split row
-    if (!mb->chi_in_lds) t = std::max(t, K <= 4 ? 1 : (K <= 16 ? 2 : 4));
+    if (t <= 0) t = (K <= 2 || (!mb->chi_in_lds && K <= 8)) ? 1 : (K <= 8 ? 2 : 4);
+    // a character table read from HBM needs an instance with at most 8
+    // sectors per lane
+    if (!mb->chi_in_lds) t = std::max(t, K <= 8 ? 1 : (K <= 16 ? 2 : 4));
     // more than 32 sectors: 4 lanes of at most 16 sectors each
     if (K > 32) t = 4;
     return t;
@@ -722,11 +743,11 @@ static int mlz_step(const ed_multi *mb, double jsq, const double2 *v, double2 *w
     int rc = multi_launch<0>(mb, v, w, w, sec, nullptr, jsq, st);
     if (rc) return rc;
     hipLaunchKernelGGL(k_mlz_dot, dim3(vgrid), dim3(kMlzThreads), 0, st, v, (const double2 *)w, D, K, W.partials);
-    hipLaunchKernelGGL(k_mlz_alpha, dim3(1), dim3(64), 0, st, (const double *)W.partials, vgrid, K, sec,
+    hipLaunchKernelGGL(k_mlz_alpha, dim3(1), dim3(kTotThreads), 0, st, (const double *)W.partials, vgrid, K, sec,
                        (const MlzState *)state, W.ahist, n_steps);
     hipLaunchKernelGGL(k_mlz_update, dim3(vgrid), dim3(kMlzThreads), 0, st, w, v, D, K, (const MlzSector *)sec,
                        W.partials);
-    hipLaunchKernelGGL(k_mlz_beta, dim3(1), dim3(64), 0, st, (const double *)W.partials, vgrid, K, sec, state, W.bhist,
+    hipLaunchKernelGGL(k_mlz_beta, dim3(1), dim3(kTotThreads), 0, st, (const double *)W.partials, vgrid, K, sec, state, W.bhist,
                        n_steps, 1e-12);
     hipLaunchKernelGGL(k_mlz_normalize, dim3(vgrid), dim3(kMlzThreads), 0, st, w, D, K, (const MlzSector *)sec);
     const hipError_t e = hipGetLastError();
@@ -790,7 +811,7 @@ int multi_lanczos(ed_multi *mb, const double *J, const void *v0, int n_steps, do
     HIP_TRY(hipMemsetAsync(W.bhist, 0, (size_t)K * n_steps * 8, st));
     hipLaunchKernelGGL(k_mlz_init_norm, dim3(vgrid), dim3(kMlzThreads), 0, st, (const double2 *)v0,
                        (const uint64_t *)mb->masks, D, K, W.partials);
-    hipLaunchKernelGGL(k_mlz_init_finish, dim3(1), dim3(64), 0, st, (const double *)W.partials, vgrid, K, sec, state);
+    hipLaunchKernelGGL(k_mlz_init_finish, dim3(1), dim3(kTotThreads), 0, st, (const double *)W.partials, vgrid, K, sec, state);
     hipLaunchKernelGGL(k_mlz_init_vec, dim3(vgrid), dim3(kMlzThreads), 0, st, (const double2 *)v0,
                        (const uint64_t *)mb->masks, D, K, (const MlzSector *)sec, B, A);
     HIP_TRY(hipGetLastError());
