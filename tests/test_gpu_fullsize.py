@@ -253,22 +253,24 @@ def test_fullsize_lanczos_two_start_vectors(name, make):
 
 # ---- batched launches at the benchmarks' own shapes ------------------------
 BATCHED = [
-    # the eight Gamma irreps of 36 T x C6v x flip: characters read from HBM
-    ("triangular36_gamma", lambda: wl.triangular_36_gamma(n_sub=4), 2, 5000),
+    # the eight Gamma irreps of 36 T x C6v x flip: characters read from HBM, one
+    # lane per row (the benchmark's instance), and two lanes per row
+    ("triangular36_gamma", lambda: wl.triangular_36_gamma(n_sub=4), None, 1, 5000),
+    ("triangular36_gamma_2lanes", lambda: wl.triangular_36_gamma(n_sub=4), {"lanes_per_row": 2}, 2, 2000),
     # the first sixteen momentum sectors, as the all-momentum benchmark groups them
-    ("triangular36_allk16", lambda: wl.triangular_36_all_momenta(n_sub=4)[:16], 4, 1500),
+    ("triangular36_allk16", lambda: wl.triangular_36_all_momenta(n_sub=4)[:16], None, 4, 1500),
 ]
 
 
-@pytest.mark.parametrize("name,make,lanes,n_rows", BATCHED, ids=[c[0] for c in BATCHED])
-def test_fullsize_batched_sampled_rows(name, make, lanes, n_rows):
+@pytest.mark.parametrize("name,make,tuning,lanes,n_rows", BATCHED, ids=[c[0] for c in BATCHED])
+def test_fullsize_batched_sampled_rows(name, make, tuning, lanes, n_rows):
     """Sector k's input is the state hash with salt k on the rows of sector k
     and a different hash elsewhere, which the kernel must ignore; sampled rows
     of every sector are compared with the oracle's row evaluation."""
     ed = _ed()
     ws = make()
     print(f"[fullsize] {name}: building {len(ws)} sectors", flush=True)
-    mb = ed.MultiBasis.from_workloads(ws)
+    mb = ed.MultiBasis.from_workloads(ws, tuning)
     try:
         info = mb.info()
         assert info["lanes_per_row"] == lanes and info["n_sublat"] == 4
