@@ -344,11 +344,11 @@ int ed_lanczos_xxz(const ed_basis_t *b, const double *Jxy, const double *Jz, con
  * is not NULL, where dH/dJ_b collects bond b's diagonal and off-diagonal
  * terms in the row form of ed_apply_H.  Synchronises if gJ_host is given.
  * gx must differ from gy and, when gJ is requested, from x (ED_ERR_ARG).
- * With both outputs on a real sector with the hash-slot index, one pass
- * computes both from a second slot table of 32 bytes per slot holding x
- * and gy.  The first such call allocates that table, and it is kept until
- * ed_free_basis.  Its gx and gJ equal, bit for bit, those of ed_apply_H on
- * gy and of this call without gx.
+ * With both outputs on a basis with the hash-slot index, one pass computes
+ * both from a second slot table holding x and gy, of 32 bytes per slot
+ * (64 for complex sectors).  The first such call allocates that table, and
+ * it is kept until ed_free_basis.  Its gx and gJ equal, bit for bit, those
+ * of ed_apply_H on gy and of this call without gx.
  */
 int ed_apply_H_backward(const ed_basis_t *b, const double *J, const void *x_dev, const void *gy_dev,
                         void *gx_dev, double *gJ_host, void *stream);

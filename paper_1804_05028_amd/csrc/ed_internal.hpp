@@ -132,8 +132,8 @@ struct ed_basis {
     double mean_candidates = 0.0;  // host Alg. 2 on random configurations
     int staged = 0;                // the H.v kernels run the two-stage search
     int fermion = 0;               // fermions in the occupation-number basis
-    // fused adjoint of real sectors: 32-byte slots {key, x, gy, -} at the
-    // positions of the 16-byte H.v slots, allocated by the first fused call
+    // fused adjoint: slots {key, x, gy} at the positions of the H.v slots
+    // (32 bytes real, 64 bytes complex), allocated by the first fused call
     // and freed with the handle
     char *adj_slots = nullptr;
     // Lanczos workspace, kept between calls and freed with the handle
@@ -179,9 +179,8 @@ int launch_apply(const ed_basis *b, const double *J, const double *Jz, const voi
                  unsigned long long *stats_dev);
 int launch_apply_timed(const ed_basis *b, const double *J, const double *Jz, const void *x, void *y, int reps,
                        double *pack_ms, double *kernel_ms, void *stream);
-// gx (may be NULL): also gx = H gy in the same pass, for real sectors with
-// the hash-slot index (the caller checks backward_fusable) and no static
-// scratch
+// gx (may be NULL): also gx = H gy in the same pass, for bases with the
+// hash-slot index (the caller checks backward_fusable) and no static scratch
 int launch_backward_J(const ed_basis *b, const double *J, const void *x, const void *gy, double *gJ_host, void *stream,
                       bool static_scratch, void *gx = nullptr);
 bool backward_fusable(const ed_basis *b);

@@ -225,42 +225,70 @@ __global__ void k_pack_cplx(const double2 *x, const uint32_t *slot_of, char *slo
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint slots: 32-byte {key, x, gy, -} at the positions of the 16-byte H.v
-// slots of a real sector (same keys, same probe sequences).
+// Adjoint slots at the positions of the H.v slots (same keys, same probe
+// sequences): 32 bytes {key, x, gy, -} for a real sector, 64 bytes
+// {key, -, x, gy, -} for a complex one (one 128-byte line either way).
 // ---------------------------------------------------------------------------
 
+template <bool CPLX>
 __global__ void k_adj_slots_keys(const char *slots, char *adj, uint64_t n_slots)
 {
+    constexpr int kIn = CPLX ? 5 : 4, kOut = CPLX ? 6 : 5;
     for (uint64_t sl = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < n_slots;
          sl += (uint64_t)gridDim.x * blockDim.x)
-        *(uint64_t *)(adj + (sl << 5)) = *(const uint64_t *)(slots + (sl << 4));
+        *(uint64_t *)(adj + (sl << kOut)) = *(const uint64_t *)(slots + (sl << kIn));
 }
 
-__global__ void k_pack_adj(const double *x, const double *gy, const uint32_t *slot_of, char *adj, int64_t D)
+template <bool CPLX>
+__global__ void k_pack_adj(const typename Scalar<CPLX>::T *x, const typename Scalar<CPLX>::T *gy,
+                           const uint32_t *slot_of, char *adj, int64_t D)
 {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < D; j += (int64_t)gridDim.x * blockDim.x) {
-        char *p = adj + ((size_t)slot_of[j] << 5);
-        *(double *)(p + 8) = x[j];
-        *(double *)(p + 16) = gy[j];
+        if (CPLX) {
+            char *p = adj + ((size_t)slot_of[j] << 6);
+            *(double2 *)(p + 16) = *(const double2 *)&x[j];
+            *(double2 *)(p + 32) = *(const double2 *)&gy[j];
+        } else {
+            char *p = adj + ((size_t)slot_of[j] << 5);
+            *(double *)(p + 8) = *(const double *)&x[j];
+            *(double *)(p + 16) = *(const double *)&gy[j];
+        }
     }
 }
 
-// probe the adjoint slots from the home slot of target: both 16-byte halves
-// of a slot are requested together; returns 1 with the packed key, x and gy
+// probe the adjoint slots from the home slot of target, every part of a slot
+// requested together; returns 1 with the packed key, x_j and gy_j
+template <bool CPLX>
 __device__ __forceinline__ int resolve_adj(const DevBasis &db, const char *adj, uint64_t sl, uint64_t target,
-                                           uint64_t &key, double &xv, double &gv)
+                                           uint64_t &key, double2 &xv, double2 &gv)
 {
     typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
     const uint64_t smask = (1ull << db.slot_log2) - 1ull;
     while (true) {
-        const u64x2 q = *(const u64x2 *)(adj + (sl << 5));
-        const u64x2 q2 = *(const u64x2 *)(adj + (sl << 5) + 16);
-        if (q.x == kEmpty) return 0;
-        if ((q.x & kStateMask) == target) {
-            key = q.x;
-            xv = __longlong_as_double((long long)q.y);
-            gv = __longlong_as_double((long long)q2.x);
-            return 1;
+        if (CPLX) {
+            const char *p = adj + (sl << 6);
+            const u64x2 q = *(const u64x2 *)p;
+            const f64x2 a = *(const f64x2 *)(p + 16);
+            const f64x2 b = *(const f64x2 *)(p + 32);
+            if (q.x == kEmpty) return 0;
+            if ((q.x & kStateMask) == target) {
+                key = q.x;
+                xv = make_double2(a.x, a.y);
+                gv = make_double2(b.x, b.y);
+                return 1;
+            }
+        } else {
+            const char *p = adj + (sl << 5);
+            const u64x2 q = *(const u64x2 *)p;
+            const u64x2 q2 = *(const u64x2 *)(p + 16);
+            if (q.x == kEmpty) return 0;
+            if ((q.x & kStateMask) == target) {
+                key = q.x;
+                xv = make_double2(__longlong_as_double((long long)q.y), 0.0);
+                gv = make_double2(__longlong_as_double((long long)q2.x), 0.0);
+                return 1;
+            }
         }
         sl = (sl + 1) & smask;
     }
@@ -273,11 +301,10 @@ __device__ __forceinline__ int resolve_adj(const DevBasis &db, const char *adj, 
 // blocks in fixed order: the result is deterministic.
 // ---------------------------------------------------------------------------
 
-// FUSED (real sectors, hash-slot index): the same pass also computes
-// gx = H gy.  Each target's x_j and gy_j come from one 32-byte slot
-// {key, x, gy, -} of adj, so one search and one line serve both products;
-// gx_i sums its terms in the order and form of k_apply, so it equals
-// ed_apply_H's H gy bit for bit.
+// FUSED (hash-slot index): the same pass also computes gx = H gy.  Each
+// target's x_j and gy_j come from one adjoint slot of adj, so one search and
+// one line serve both products; gx_i sums its terms in the order and form of
+// k_apply, so it equals ed_apply_H's H gy bit for bit.
 template <bool CPLX, typename AT, int INDEX, int NSC, bool FUSED = false>
 __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, const typename Scalar<CPLX>::T *__restrict__ x,
                                                      const typename Scalar<CPLX>::T *__restrict__ gy,
@@ -285,7 +312,7 @@ __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, c
                                                      const char *__restrict__ adj = nullptr, double *__restrict__ gx = nullptr,
                                                      double jsum_quarter = 0.0)
 {
-    static_assert(!FUSED || (!CPLX && INDEX == IDX_HASH), "the fused adjoint covers real sectors with hash slots");
+    static_assert(!FUSED || INDEX == IDX_HASH, "the fused adjoint reads hash slots");
     // A_b = 1/4 sum_i Re(conj(gy_i) x_i)                      (every bond parallel)
     //     + sum_{i: b antiparallel} [ -1/2 Re(conj(gy_i) x_i) + Re(conj(gy_i) t_b(i)) ]
     // where t_b(i) is the flip term of bond b in row i.  Column nb of the
@@ -321,7 +348,7 @@ __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, c
             }
         }
         tot += wave_sum(gx_r);
-        double anti_sum = 0.0, ar = 0.0;   // FUSED: diagonal and off-diagonal parts of (H gy)_i
+        double anti_sum = 0.0, ar = 0.0, ai = 0.0;   // FUSED: diagonal and off-diagonal parts of (H gy)_i
         for (int b = 0; b < nb; ++b) {
             const BondLds bd = c.bonds[b];
             const uint64_t t = s & bd.mask;
@@ -334,20 +361,21 @@ __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, c
                 uint32_t g;
                 const uint64_t r = rep_search<AT, NSC>(c, s ^ bd.mask, g);
                 uint64_t key;
-                double xj, gj;
-                if (resolve_adj(db, adj, slot_of_state(r, db.slot_log2), r, key, xj, gj)) {
+                double2 xj, gj;
+                if (resolve_adj<CPLX>(db, adj, slot_of_state(r, db.slot_log2), r, key, xj, gj)) {
                     double cr, ci;
-                    chi_of<false>(c, g, cr, ci);
+                    chi_of<CPLX>(c, g, cr, ci);
                     const double sq = c.div_sqrt[key >> kNormShift];
                     // the per-bond term exactly as the unfused branch forms it
-                    const double vr = xj, vi = 0.0;
+                    const double vr = xj.x, vi = CPLX ? xj.y : 0.0;
                     const double amp = 0.5 * sq * rs_i;
                     const double tr = amp * (cr * vr - ci * vi), ti = amp * (cr * vi + ci * vr);
                     contrib += g_r * tr + g_i * ti;
                     // and the H gy term exactly as k_apply forms it
-                    const double wr = gj, wi = 0.0;
+                    const double wr = gj.x, wi = CPLX ? gj.y : 0.0;
                     const double ampg = bd.jhalf * rs_i * c.div_sqrt[key >> kNormShift];
                     ar += ampg * (cr * wr - ci * wi);
+                    if (CPLX) ai += ampg * (cr * wi + ci * wr);
                 }
             } else if (anti) {
                 contrib = -0.5 * gx_r;
@@ -398,7 +426,17 @@ __global__ void __launch_bounds__(1024) k_backward_J(DevModel dm, DevBasis db, c
                 else a3 += wsum;
             }
         }
-        if (FUSED && valid) gx[i] = (jsum_quarter - anti_sum) * g_r + ar;
+        if (FUSED && valid) {
+            const double d = jsum_quarter - anti_sum;
+            if (CPLX) {
+                double2 out;
+                out.x = d * g_r + ar;
+                out.y = d * g_i + ai;
+                *(double2 *)&gx[2 * i] = out;
+            } else {
+                gx[i] = d * g_r + ar;
+            }
+        }
     }
     // block reduction in fixed order (the tables are no longer needed)
     __syncthreads();
@@ -1477,21 +1515,24 @@ static int backward_impl(const ed_basis *b, const void *x, const void *gy, doubl
 
 bool backward_fusable(const ed_basis *b)
 {
-    return !b->dm.is_complex && b->db.index_mode == IDX_HASH && !b->fermion;
+    return b->db.index_mode == IDX_HASH && !b->fermion;
 }
 
-// 32-byte adjoint slots of a real sector, made once per basis: keys copied
-// from the H.v slots
+// adjoint slots, made once per basis: keys copied from the H.v slots
 static int ensure_adj_slots(const ed_basis *bc, hipStream_t st)
 {
     ed_basis *b = const_cast<ed_basis *>(bc);
     if (b->adj_slots) return ED_OK;
+    const bool c = b->dm.is_complex;
     void *p = nullptr;
-    int rc = device_alloc(b, &p, (size_t)b->n_slots * 32);
+    int rc = device_alloc(b, &p, (size_t)b->n_slots * (c ? 64 : 32));
     if (rc) return rc;
     const uint64_t n = (uint64_t)b->n_slots;
-    hipLaunchKernelGGL(k_adj_slots_keys, dim3((unsigned)std::min<uint64_t>((n + 255) / 256, 1u << 20)), dim3(256), 0, st,
-                       (const char *)b->db.slots, (char *)p, n);
+    const dim3 grid((unsigned)std::min<uint64_t>((n + 255) / 256, 1u << 20));
+    if (c)
+        hipLaunchKernelGGL(k_adj_slots_keys<true>, grid, dim3(256), 0, st, (const char *)b->db.slots, (char *)p, n);
+    else
+        hipLaunchKernelGGL(k_adj_slots_keys<false>, grid, dim3(256), 0, st, (const char *)b->db.slots, (char *)p, n);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(ED_ERR_HIP, "adjoint slot setup failed: %s", hipGetErrorString(e));
     b->adj_slots = (char *)p;
@@ -1532,16 +1573,25 @@ int launch_backward_J(const ed_basis *b, const double *J, const void *x, const v
         rc = ensure_adj_slots(b, st);
         if (rc) return rc;
         const int64_t D = b->db.dim;
-        hipLaunchKernelGGL(k_pack_adj, dim3((unsigned)std::min<int64_t>((D + 255) / 256, 1 << 20)), dim3(256), 0, st,
-                           (const double *)x, (const double *)gy, b->db.slot_of, b->adj_slots, D);
+        const dim3 pgrid((unsigned)std::min<int64_t>((D + 255) / 256, 1 << 20));
+        if (c)
+            hipLaunchKernelGGL(k_pack_adj<true>, pgrid, dim3(256), 0, st, (const double2 *)x, (const double2 *)gy,
+                               b->db.slot_of, b->adj_slots, D);
+        else
+            hipLaunchKernelGGL(k_pack_adj<false>, pgrid, dim3(256), 0, st, (const double *)x, (const double *)gy,
+                               b->db.slot_of, b->adj_slots, D);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return set_error(ED_ERR_HIP, "adjoint pack failed: %s", hipGetErrorString(e));
-#define ED_FCASE(A, K) \
-    if (w == (int)sizeof(A) && nsc == K) return backward_impl<false, A, IDX_HASH, K, true>(b, x, gy, gJ_host, nullptr, st, gx, jsq);
-#define ED_FCASES(A) ED_FCASE(A, 0) ED_FCASE(A, 33) ED_FCASE(A, 34) ED_FCASE(A, 35)
-        ED_FCASES(uint8_t)
-        ED_FCASES(uint16_t)
-        ED_FCASES(uint32_t)
+#define ED_FCASE(C, A, K) \
+    if (c == C && w == (int)sizeof(A) && nsc == K) \
+        return backward_impl<C, A, IDX_HASH, K, true>(b, x, gy, gJ_host, nullptr, st, gx, jsq);
+#define ED_FCASES(C, A) ED_FCASE(C, A, 0) ED_FCASE(C, A, 33) ED_FCASE(C, A, 34) ED_FCASE(C, A, 35)
+        ED_FCASES(false, uint8_t)
+        ED_FCASES(false, uint16_t)
+        ED_FCASES(false, uint32_t)
+        ED_FCASES(true, uint8_t)
+        ED_FCASES(true, uint16_t)
+        ED_FCASES(true, uint32_t)
 #undef ED_FCASES
 #undef ED_FCASE
         return set_error(ED_ERR_ARG, "no kernel variant");

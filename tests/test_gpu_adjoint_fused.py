@@ -1,11 +1,12 @@
-"""The fused adjoint pass of real sectors (gx = H gy and the per-bond sums
-gJ in one pass over the terms, reading x_j and gy_j from one 32-byte slot)
+"""The fused adjoint pass (gx = H gy and the per-bond sums gJ in one pass
+over the terms, reading x_j and gy_j from one adjoint slot: 32 bytes for
+real sectors, 64 for complex ones)
 against the separate products: gx against ed_apply_H on gy, gJ against the
 per-bond kernel alone (ed_apply_H_backward without gx).  Both are formed
 term by term in the same order and form, so they must agree bit for bit.
-Covers 1-, 2- and 4-byte tables, one to three compile-time chunks, the
-run-time search loops, and the 32-site disorder workload of the adjoint
-benchmark at full size."""
+Covers real and complex sectors, 1-, 2- and 4-byte tables, one to three
+compile-time chunks, the run-time search loops, and the 32-site disorder
+workload of the adjoint benchmark at full size."""
 import numpy as np
 import pytest
 import torch
@@ -24,7 +25,17 @@ CASES = [
     ("sq20_n5", lambda: wl.square_20_j1j2(n_sub=5), None),
     ("tri12_full", lambda: wl.triangular_12(), None),
     ("square32_disorder", lambda: _disorder32(), None),
+    ("square16_k3_complex", lambda: wl.square_4x4(momentum_index=3), None),
+    ("sq20_n4_k1_complex", lambda: _sq20_momentum(1), {"chunk_bits": 3}),
+    ("square16_k5_complex_u8", lambda: wl.square_4x4(momentum_index=5), {"table_entry_bytes": 1}),
 ]
+
+
+def _sq20_momentum(k):
+    """The 20-site J1-J2 cluster, translations only, momentum sector k (complex)."""
+    w = wl.square_20_j1j2(n_sub=4)
+    c = lat.square((4, 2), (-2, 4), j2=True, rotations=False, mirrors=False, superlattice=wl.SQ_2X2, name="sq20T")
+    return wl.Workload("sq20T_k", c, lat.characters(c, k), w.n_up, np.array([1.0, 0.5])[c.bond_kind])
 
 
 def _disorder32():
@@ -42,10 +53,9 @@ def test_fused_adjoint_equals_separate_products(name, make, tuning):
     w = make()
     b = ed.Basis.from_workload(w, tuning)
     try:
-        assert not b.is_complex
         J = np.asarray(w.J, dtype=np.float64)
-        x = torch.as_tensor(vec.normal_vector(b.dim, seed=11)).cuda()
-        gy = torch.as_tensor(vec.normal_vector(b.dim, seed=12)).cuda()
+        x = torch.as_tensor(vec.normal_vector(b.dim, seed=11, complex_=b.is_complex)).cuda()
+        gy = torch.as_tensor(vec.normal_vector(b.dim, seed=12, complex_=b.is_complex)).cuda()
         print(f"[fused] {name}: D={b.dim}", flush=True)
         gx = b.empty()
         gJ = L.ed_apply_H_backward(b.handle, J, x, gy, gx, True, None)        # fused pass
