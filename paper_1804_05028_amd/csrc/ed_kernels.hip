@@ -256,18 +256,22 @@ __global__ void k_pack_adj(const typename Scalar<CPLX>::T *x, const typename Sca
     }
 }
 
-// probe the adjoint slots from the home slot of target, every part of a slot
-// requested together; returns 1 with the packed key, x_j and gy_j
+// probe the adjoint slots from the home slot of target; returns 1 with the
+// packed key, x_j and gy_j.  A real slot is one 32-byte vector load, so its
+// two 16-byte halves are requested together (loaded as two 16-byte values,
+// the compiler waits for the key half before it issues the other).  Complex
+// slots read the key first and the amplitudes of the matching slot only.
 template <bool CPLX>
 __device__ __forceinline__ int resolve_adj(const DevBasis &db, const char *adj, uint64_t sl, uint64_t target,
                                            uint64_t &key, double2 &xv, double2 &gv)
 {
     typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    typedef unsigned long long u64x4 __attribute__((ext_vector_type(4)));
     typedef double f64x2 __attribute__((ext_vector_type(2)));
     const uint64_t smask = (1ull << db.slot_log2) - 1ull;
     while (true) {
         if (CPLX) {
-            const char *p = adj + (sl << 6);
+            const char *p = adj + (sl << 6);   // {key, -, x.re, x.im, gy.re, gy.im, -, -}
             const u64x2 q = *(const u64x2 *)p;
             const f64x2 a = *(const f64x2 *)(p + 16);
             const f64x2 b = *(const f64x2 *)(p + 32);
@@ -279,14 +283,12 @@ __device__ __forceinline__ int resolve_adj(const DevBasis &db, const char *adj, 
                 return 1;
             }
         } else {
-            const char *p = adj + (sl << 5);
-            const u64x2 q = *(const u64x2 *)p;
-            const u64x2 q2 = *(const u64x2 *)(p + 16);
-            if (q.x == kEmpty) return 0;
-            if ((q.x & kStateMask) == target) {
-                key = q.x;
-                xv = make_double2(__longlong_as_double((long long)q.y), 0.0);
-                gv = make_double2(__longlong_as_double((long long)q2.x), 0.0);
+            const u64x4 q = *(const u64x4 *)(adj + (sl << 5));   // {key, x, gy, -}
+            if (q[0] == kEmpty) return 0;
+            if ((q[0] & kStateMask) == target) {
+                key = q[0];
+                xv = make_double2(__longlong_as_double((long long)q[1]), 0.0);
+                gv = make_double2(__longlong_as_double((long long)q[2]), 0.0);
                 return 1;
             }
         }

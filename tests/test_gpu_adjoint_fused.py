@@ -5,8 +5,9 @@ against the separate products: gx against ed_apply_H on gy, gJ against the
 per-bond kernel alone (ed_apply_H_backward without gx).  Both are formed
 term by term in the same order and form, so they must agree bit for bit.
 Covers real and complex sectors, 1-, 2- and 4-byte tables, one to three
-compile-time chunks, the run-time search loops, and the 32-site disorder
-workload of the adjoint benchmark at full size."""
+compile-time chunks, the run-time search loops, 512- and 1024-thread blocks
+(rows on the second and later waves of every SIMD), and the 32-site
+disorder workload of the adjoint benchmark at full size."""
 import numpy as np
 import pytest
 import torch
@@ -28,6 +29,12 @@ CASES = [
     ("square16_k3_complex", lambda: wl.square_4x4(momentum_index=3), None),
     ("sq20_n4_k1_complex", lambda: _sq20_momentum(1), {"chunk_bits": 3}),
     ("square16_k5_complex_u8", lambda: wl.square_4x4(momentum_index=5), {"table_entry_bytes": 1}),
+    # 1024-thread blocks: rows on the second and later waves of each SIMD
+    ("square16_k0_1024", lambda: wl.square_4x4(), {"block_threads": 1024}),
+    ("square16_k3_complex_1024", lambda: wl.square_4x4(momentum_index=3), {"block_threads": 1024}),
+    ("square16_k5_complex_u8_1024", lambda: wl.square_4x4(momentum_index=5), {"table_entry_bytes": 1, "block_threads": 1024}),
+    ("sq20_n4_u8_1024", lambda: wl.square_20_j1j2(n_sub=4), {"table_entry_bytes": 1, "block_threads": 1024}),
+    ("sq20_n4_k1_complex_1024", lambda: _sq20_momentum(1), {"chunk_bits": 3, "block_threads": 1024}),
 ]
 
 
