@@ -46,13 +46,13 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_05028_amd", "csrc", f)
 MEASURED_TRAFFIC = {
     # (workload, n_sublat, index, chunk_bits): (kernel sha256, fetch bytes, write bytes, profile)
     ("square40_j1j2", 4, "hash-slot", 5): (
-        "3a03a717145007ece6766196f7477f891a1fe224e5389d28fe2182494061119c", 4.72873e+12, 3.44728e+09,
+        "7f4c46799b0f61cbb1a8944b52d820eaefcd5e41a2cb876928bddaa42ec080e1", 4.72875e+12, 3.44728e+09,
         "profiles/k_apply_square40_j1j2_ns4.md"),
     ("triangular36_k1", 4, "hash-slot", 5): (
-        "3a03a717145007ece6766196f7477f891a1fe224e5389d28fe2182494061119c", 1.94339e+12, 4.03337e+09,
+        "7f4c46799b0f61cbb1a8944b52d820eaefcd5e41a2cb876928bddaa42ec080e1", 1.94326e+12, 4.03337e+09,
         "profiles/k_apply_triangular36_k1_complex.md"),
     ("triangular36_tV", 4, "hash-slot", 3): (
-        "3a03a717145007ece6766196f7477f891a1fe224e5389d28fe2182494061119c", 3.03090e+11, 3.36083e+08,
+        "7f4c46799b0f61cbb1a8944b52d820eaefcd5e41a2cb876928bddaa42ec080e1", 3.03108e+11, 3.36083e+08,
         "profiles/k_apply_fermions_triangular36_tV.md"),
 }
 
