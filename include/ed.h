@@ -289,8 +289,11 @@ int ed_apply_H_xxz(const ed_basis_t *b, const double *Jxy, const double *Jz, con
  * orbitals per site (the group permuting both species alike).
  *
  * ed_build_basis_fermions: as ed_build_basis with n_particles occupied
- * orbitals; ED_ERR_UNSUPPORTED for flip elements, the Limits index, 1- or
- * 2-byte table entries, or blocks of more than 16 orbitals.
+ * orbitals; ED_ERR_UNSUPPORTED for flip elements, the Limits index, 1-byte
+ * table entries, 2-byte entries with blocks of more than 12 orbitals or more
+ * than 8 sublattices, or blocks of more than 16 orbitals.  table_entry_bytes
+ * 0 takes 2-byte entries (the chunk's sign parity in bit 15) where they fit,
+ * else 4-byte ones (parity in bit 31).
  *
  * ed_apply_H_fermions: y = H x for
  *   H = sum_b [ -t_b (c+_p c_q + c+_q c_p) + V_b n_p n_q ],

@@ -166,9 +166,16 @@ static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, co
                 delete b;
                 return set_error(ED_ERR_UNSUPPORTED, "element %d of a fermionic group carries a spin flip", g);
             }
-        if (b->tuning.index_mode != 0 || (b->tuning.table_entry_bytes != 0 && b->tuning.table_entry_bytes != 4)) {
+        const int eb = b->tuning.table_entry_bytes;
+        if (b->tuning.index_mode != 0 || (eb != 0 && eb != 2 && eb != 4)) {
             delete b;
-            return set_error(ED_ERR_UNSUPPORTED, "fermionic bases use the hash-slot index and 4-byte table entries");
+            return set_error(ED_ERR_UNSUPPORTED, "fermionic bases use the hash-slot index and 2- or 4-byte table entries");
+        }
+        if (eb == 2 && (b->t.m > 12 || b->t.ns > 8)) {
+            delete b;
+            return set_error(ED_ERR_UNSUPPORTED,
+                             "2-byte fermionic table entries need blocks of at most 12 orbitals and at most 8 "
+                             "sublattices (%d, %d)", b->t.m, b->t.ns);
         }
         if (b->t.m > 16) {
             delete b;

@@ -94,14 +94,33 @@ __device__ __forceinline__ Ctx<AT> stage(const DevModel &dm, char *lds)
     return c;
 }
 
+// 2-byte action-table entry of a fermionic basis: the image in bits 0-11,
+// the target block index in bits 12-14 (chunk 0), and the parity of the
+// orbital pairs inside the chunk whose order the element reverses in bit 15.
+// A type of its own, so that the spin tables' 2-byte entries (block index in
+// bits 12-15) keep their layout and their kernels' code.
+struct FermiU16 {
+    uint16_t v;
+    __device__ __forceinline__ operator uint32_t() const { return v; }
+};
+
 // Action-table entries: uint8 holds the image pattern only (its block
 // position comes from the shift table); uint16 / uint32 entries of chunk 0
 // also carry the target block index above bit 12 / 16, which saves that
-// lookup.
+// lookup.  kParity: the bit of fermionic entries holding the chunk's parity.
 template <typename AT>
 struct ActTraits {
     static constexpr bool kPos = sizeof(AT) > 1;
     static constexpr int kPosShift = sizeof(AT) == 2 ? 12 : 16;
+    static constexpr uint32_t kPosMask = sizeof(AT) == 4 ? 0xFFu : 0u;   // 0: every bit above the image
+    static constexpr int kParity = 31;
+};
+template <>
+struct ActTraits<FermiU16> {
+    static constexpr bool kPos = true;
+    static constexpr int kPosShift = 12;
+    static constexpr uint32_t kPosMask = 0x7u;
+    static constexpr int kParity = 15;
 };
 
 template <typename AT>
@@ -109,8 +128,9 @@ __device__ __forceinline__ uint64_t place_block(const Ctx<AT> &c, uint32_t u, in
 {
     if (ActTraits<AT>::kPos) {
         const uint32_t img = e & ((1u << ActTraits<AT>::kPosShift) - 1u);
-        // 4-byte entries keep bits 24-31 for fermionic sign parities
-        const uint32_t pos = sizeof(AT) == 4 ? (e >> 16) & 0xFFu : e >> ActTraits<AT>::kPosShift;
+        // fermionic entries keep their top bit for the sign parity
+        const uint32_t pos = ActTraits<AT>::kPosMask ? (e >> ActTraits<AT>::kPosShift) & ActTraits<AT>::kPosMask
+                                                     : e >> ActTraits<AT>::kPosShift;
         // position and block width are below 2^24: full-rate 24-bit multiply
         return (uint64_t)img << ((uint32_t)(c.N - c.m) - __umul24(pos, (uint32_t)c.m));
     }
@@ -363,11 +383,14 @@ __device__ __forceinline__ uint64_t find_rep_staged(const Ctx<AT> &c, uint64_t s
 // pairs in one chunk come from the parity bit of the chunk's table entry, and
 // pairs in two chunks of one block from the chunk images: for the chunks in
 // source order, the pairs an image forms with the images of the earlier
-// chunks that land below it.  Returns the parity (0 or 1); 4-byte entries.
+// chunks that land below it.  Returns the parity (0 or 1); 4-byte entries
+// or the 2-byte fermionic ones.
 template <typename AT, int NSC = 0>
 __device__ __forceinline__ uint32_t fermi_parity(const Ctx<AT> &c, uint32_t u, uint64_t s)
 {
-    static_assert(sizeof(AT) == 4, "fermionic tables use 4-byte entries");
+    using Tr = ActTraits<AT>;
+    static_assert(sizeof(AT) == 4 || Tr::kParity == 15, "fermionic tables use 4-byte or FermiU16 entries");
+    constexpr uint32_t kImg = (1u << Tr::kPosShift) - 1u;
     // sublattice and chunk counts fixed at compile time when NSC gives them
     constexpr int NS_ = (NSC & 127) / 8, NC_ = NSC % 8;
     const int ns = NS_ > 0 ? NS_ : c.ns, nc = NC_ > 0 ? NC_ : c.nc;
@@ -381,15 +404,15 @@ __device__ __forceinline__ uint32_t fermi_parity(const Ctx<AT> &c, uint32_t u, u
 #pragma unroll
         for (int k = nc - 1; k >= 0; --k) {   // chunk nc-1 holds the block's first orbitals
             const uint32_t e = t[(k << c.cb) | ((sx >> (k * c.cb)) & c.cmask)];
-            const uint32_t img = e & 0xFFFFu;
+            const uint32_t img = e & kImg;
             uint32_t px = earlier;               // px bit j: parity of earlier image bits at or below j
             px ^= px << 1;
             px ^= px << 2;
             px ^= px << 4;
             px ^= px << 8;
-            par ^= (e >> 31) ^ ((uint32_t)__popc(img & (px << 1)) & 1u);
+            par ^= ((e >> Tr::kParity) & 1u) ^ ((uint32_t)__popc(img & (px << 1)) & 1u);
             earlier |= img;
-            if (k == 0) pos = (e >> 16) & 0xFFu;
+            if (k == 0) pos = (e >> Tr::kPosShift) & Tr::kPosMask;
         }
         const uint32_t odd = (uint32_t)__popc(sx) & 1u;
         par ^= odd & ((uint32_t)__popcll(seen >> (pos + 1)) & 1u);

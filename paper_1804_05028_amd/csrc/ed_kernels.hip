@@ -29,7 +29,7 @@ namespace ed {
 // w = H v - beta_prev v_prev with per-block <v, w> partial sums.
 // ---------------------------------------------------------------------------
 
-// FERMI: fermions in the occupation-number basis (4-byte tables, hash
+// FERMI: fermions in the occupation-number basis (4-byte or FermiU16 tables, hash
 // index): a flip of bond b is the hop -t_b (c+_p c_q + h.c.) with sign
 // (-1)^(occupied orbitals between p and q) times the Fermi sign of the
 // element mapping the hopped configuration to its representative, and the
@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(256) k_basis_enum(DevModel dm, BuildParams bp,
                                 // the symmetrised state survives iff chi(g) equals the action's
                                 // sign on the stabiliser: 1 for spins, the Fermi sign for fermions
                                 double sign = 1.0;
-                                if constexpr (sizeof(AT) == 4) {
+                                if constexpr (sizeof(AT) == 4 || ActTraits<AT>::kParity == 15) {
                                     if (dm.fermion && fermi_parity(c, (ent >> 16) & 0x7FFFu, sgm)) sign = -1.0;
                                 }
                                 if (!dm.trivial_irrep || sign < 0.0) {
@@ -917,7 +917,7 @@ static int upload_tables(ed_basis *b, hipStream_t st)
                                 for (int a = 0; a < width; ++a)
                                     for (int c2 = 0; c2 < a; ++c2)
                                         if ((v >> a & 1u) && (v >> c2 & 1u) && ib[a] < ib[c2]) par ^= 1u;
-                                img |= par << 31;
+                                img |= par << (esz == 2 ? 15 : 31);
                             }
                             const size_t idx = ((((size_t)u * ns + X) * nc + k) << cb) | v;
                             memcpy(&act[idx * esz], &img, esz);   // little endian: low bytes
@@ -937,8 +937,11 @@ static int upload_tables(ed_basis *b, hipStream_t st)
     // LDS budget, a wide entry if it fits at that chunk count; for a given
     // chunk count the narrowest equal split is the smallest table.
     const int wide = m <= 12 ? 2 : 4;
-    // fermionic sign parities live in bit 31 of 4-byte entries
-    int want_esz = b->fermion ? 4 : b->tuning.table_entry_bytes;
+    // fermionic sign parities live in bit 15 of 2-byte entries (images of up
+    // to 12 orbitals, block index below 8 in bits 12-14) or in bit 31 of
+    // 4-byte ones; automatic choice: 2 bytes where they fit
+    const bool fermi16 = m <= 12 && ns <= 8;
+    int want_esz = b->fermion ? (b->tuning.table_entry_bytes == 4 || !fermi16 ? 4 : 2) : b->tuning.table_entry_bytes;
     if (want_esz == 1 && m > 8) want_esz = wide;
     if (want_esz == 2 && m > 12) want_esz = 4;
     int cb = m, esz = want_esz ? want_esz : wide;
@@ -1256,7 +1259,7 @@ int launch_basis_build(ed_basis *b, void *stream)
     int rc = upload_tables(b, st);
     if (rc) return rc;
     if (b->dm.act_bytes == 1) return build_impl<uint8_t>(b, st);
-    if (b->dm.act_bytes == 2) return build_impl<uint16_t>(b, st);
+    if (b->dm.act_bytes == 2) return b->fermion ? build_impl<FermiU16>(b, st) : build_impl<uint16_t>(b, st);
     return build_impl<uint32_t>(b, st);
 }
 
@@ -1346,22 +1349,30 @@ static int apply_dispatch_t(const ed_basis *b, const void *x, void *y, const voi
     return apply_ns<MODE, false, AT>(b, x, y, vprev, partials, stats, lz, jsq, st);
 }
 
+// fermions: four sublattices with two or three chunks fix both counts at
+// compile time; other shapes read them at run time
+template <int MODE, typename AT>
+static int apply_fermi(const ed_basis *b, const void *x, void *y, const void *vprev, double *partials,
+                       unsigned long long *stats, const LzState *lz, double jsq, hipStream_t st)
+{
+    const bool c = b->dm.is_complex;
+    if (b->dm.ns == 4 && b->dm.n_chunks == 3)
+        return c ? apply_impl<true, AT, IDX_HASH, MODE, 35, true>(b, x, y, vprev, partials, stats, lz, jsq, st)
+                 : apply_impl<false, AT, IDX_HASH, MODE, 35, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    if (b->dm.ns == 4 && b->dm.n_chunks == 2)
+        return c ? apply_impl<true, AT, IDX_HASH, MODE, 34, true>(b, x, y, vprev, partials, stats, lz, jsq, st)
+                 : apply_impl<false, AT, IDX_HASH, MODE, 34, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    return c ? apply_impl<true, AT, IDX_HASH, MODE, 0, true>(b, x, y, vprev, partials, stats, lz, jsq, st)
+             : apply_impl<false, AT, IDX_HASH, MODE, 0, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
+}
+
 template <int MODE>
 static int apply_dispatch(const ed_basis *b, const void *x, void *y, const void *vprev, double *partials,
                           unsigned long long *stats, const LzState *lz, double jsq, hipStream_t st)
 {
-    if (b->fermion) {   // 4-byte tables, hash index, one-stage search
-        // four sublattices with two or three chunks: both counts fixed at
-        // compile time; other shapes read them at run time
-        const bool c = b->dm.is_complex;
-        if (b->dm.ns == 4 && b->dm.n_chunks == 3)
-            return c ? apply_impl<true, uint32_t, IDX_HASH, MODE, 35, true>(b, x, y, vprev, partials, stats, lz, jsq, st)
-                     : apply_impl<false, uint32_t, IDX_HASH, MODE, 35, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
-        if (b->dm.ns == 4 && b->dm.n_chunks == 2)
-            return c ? apply_impl<true, uint32_t, IDX_HASH, MODE, 34, true>(b, x, y, vprev, partials, stats, lz, jsq, st)
-                     : apply_impl<false, uint32_t, IDX_HASH, MODE, 34, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
-        return c ? apply_impl<true, uint32_t, IDX_HASH, MODE, 0, true>(b, x, y, vprev, partials, stats, lz, jsq, st)
-                 : apply_impl<false, uint32_t, IDX_HASH, MODE, 0, true>(b, x, y, vprev, partials, stats, lz, jsq, st);
+    if (b->fermion) {   // 2- or 4-byte tables, hash index, one-stage search
+        if (b->dm.act_bytes == 2) return apply_fermi<MODE, FermiU16>(b, x, y, vprev, partials, stats, lz, jsq, st);
+        return apply_fermi<MODE, uint32_t>(b, x, y, vprev, partials, stats, lz, jsq, st);
     }
     if (b->dm.act_bytes == 1) return apply_dispatch_t<MODE, uint8_t>(b, x, y, vprev, partials, stats, lz, jsq, st);
     if (b->dm.act_bytes == 2) return apply_dispatch_t<MODE, uint16_t>(b, x, y, vprev, partials, stats, lz, jsq, st);

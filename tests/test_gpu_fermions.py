@@ -58,6 +58,17 @@ def _cases():
     for k in (0, 1, 2):
         out.append((wl.hubbard_ring(4, 1.0, 2.5, momentum_index=k, n_sub=2), None))
     out.append((wl.hubbard_ring(6, 1.0, 4.0, momentum_index=1, n_sub=4), None))
+    # 4-byte entries (sign parity in bit 31) beside the automatic 2-byte ones
+    # (bit 15); one to three chunks
+    c = lat.triangular((2, 2), (-2, 4), superlattice=wl.TRI_4, name="tri12_4sub")
+    out.append((_fw("tri12_G0_e4", c, lat.characters(c, 0), 5, V=0.5), {"table_entry_bytes": 4}))
+    out.append((_fw("tri12_G0_e4_c1", c, lat.characters(c, 0), 6, V=1.0), {"table_entry_bytes": 4, "chunk_bits": 1}))
+    c = lat.square((4, 0), (0, 4), superlattice=wl.SQ_2X2, name="sq16C4")
+    U, det = lat.momenta(c)
+    km = U.index((det // 2, det // 2))
+    out.append((_fw("sq16_M_e4", c, lat.characters(c, km), 7, V=0.5), {"table_entry_bytes": 4, "chunk_bits": 2}))
+    out.append((_fw("sq16_M_e2", c, lat.characters(c, km), 7, V=0.5), {"table_entry_bytes": 2, "chunk_bits": 3}))
+    out.append((wl.hubbard_ring(6, 1.0, 4.0, momentum_index=1, n_sub=4), {"table_entry_bytes": 4}))
     return out
 
 
@@ -82,7 +93,10 @@ def test_fermion_basis_hv_and_lanczos(w, tune):
     b = ed.FermionBasis.from_workload(w, tune)
     try:
         info = b.info()
-        assert info["is_fermion"] == 1 and info["table_entry_bytes"] == 4
+        assert info["is_fermion"] == 1
+        # 2-byte entries wherever a block has at most 12 orbitals, unless 4 are asked for
+        want = (tune or {}).get("table_entry_bytes", 0) or (2 if info["sub_bits"] <= 12 else 4)
+        assert info["table_entry_bytes"] == want
         assert b.dim == len(st)
         if b.dim == 0:
             return
@@ -125,6 +139,13 @@ def test_fermion_entry_points_reject_the_other_kind():
         with pytest.raises(L.EDError) as e:
             L.ed_apply_H_backward(fb.handle, w.t, x, x, y, True)
         assert e.value.name == "ED_ERR_UNSUPPORTED"
+        # 1-byte entries, and 2-byte ones for blocks of more than 12 orbitals
+        c16 = lat.chain(16, superlattice_period=None)
+        w16 = _fw("ring16_1sub", c16, lat.characters(c16, 0), 3)
+        for eb in (1, 2):
+            with pytest.raises(L.EDError) as e:
+                ed.FermionBasis.from_workload(w16, {"table_entry_bytes": eb})
+            assert e.value.name == "ED_ERR_UNSUPPORTED"
         # couplings that break the group
         t = w.t.copy()
         t[0] = 2.0
@@ -154,6 +175,9 @@ def test_fermion_fullsize_sampled_rows():
         b = ed.FermionBasis.from_workload(w)
         try:
             D = b.dim
+            info = b.info()
+            print(f"[fermions] {w.name}: {info['table_entry_bytes']}-byte entries, {info['chunk_bits']}-bit chunks, "
+                  f"{info['lds_bytes']} B of LDS", flush=True)
             assert D == odim.fermion_sector_dimension(c.perm, w.chi, w.n_part)
             st = b.states_device()
             assert bool((st[1:] > st[:-1]).all())
