@@ -46,13 +46,13 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_05028_amd", "csrc", f)
 MEASURED_TRAFFIC = {
     # (workload, n_sublat, index, chunk_bits): (kernel sha256, fetch bytes, write bytes, profile)
     ("square40_j1j2", 4, "hash-slot", 5): (
-        "7f4c46799b0f61cbb1a8944b52d820eaefcd5e41a2cb876928bddaa42ec080e1", 4.72875e+12, 3.44728e+09,
+        "c0a245174c42acaf7d76a1a9fb76fb30324ded420c2f46e8d9a3bf1e544b2b62", 4.72864e+12, 3.44728e+09,
         "profiles/k_apply_square40_j1j2_ns4.md"),
     ("triangular36_k1", 4, "hash-slot", 5): (
-        "7f4c46799b0f61cbb1a8944b52d820eaefcd5e41a2cb876928bddaa42ec080e1", 1.94326e+12, 4.03337e+09,
+        "c0a245174c42acaf7d76a1a9fb76fb30324ded420c2f46e8d9a3bf1e544b2b62", 1.94341e+12, 4.03337e+09,
         "profiles/k_apply_triangular36_k1_complex.md"),
-    ("triangular36_tV", 4, "hash-slot", 3): (
-        "7f4c46799b0f61cbb1a8944b52d820eaefcd5e41a2cb876928bddaa42ec080e1", 3.03108e+11, 3.36083e+08,
+    ("triangular36_tV", 4, "hash-slot", 5): (
+        "c0a245174c42acaf7d76a1a9fb76fb30324ded420c2f46e8d9a3bf1e544b2b62", 3.05603e+11, 3.36083e+08,
         "profiles/k_apply_fermions_triangular36_tV.md"),
 }
 
