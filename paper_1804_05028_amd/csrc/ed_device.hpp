@@ -466,6 +466,22 @@ __device__ __forceinline__ uint64_t slot_of_state(uint64_t s, int log2n)
     return log2n ? (s >> (64 - log2n)) : 0ull;
 }
 
+// Probe sequence of the slot table, the same for every insertion and every
+// lookup.  Slots are visited a 128-byte line at a time: from the home slot
+// round its own line (8 slots of 16 bytes, or 4 of 32: GLOG2 = 3 or 2), then
+// round the next line from the same offset, and so on; every slot comes once
+// in 2^slot_log2 steps.  A key whose home slot is taken stays in the home
+// line unless that line is full, so a lookup reads one line however far it
+// probes inside it (plain linear probing leaves the line whenever the home
+// slot is near its end).  Tables hold at least 16 slots.
+__device__ __forceinline__ uint64_t next_slot(uint64_t sl, uint64_t home, uint64_t smask, int glog2)
+{
+    const uint64_t gm = (1ull << glog2) - 1ull;
+    uint64_t nx = (sl & ~gm) | ((sl + 1ull) & gm);
+    if (((nx ^ home) & gm) == 0) nx = (nx + gm + 1ull) & smask;
+    return nx;
+}
+
 // first 16 bytes of a slot: {key, x} (real) or {key, -} (complex).  Slot
 // reads are random and rarely reused, yet ordinary loads measure faster than
 // non-temporal ones: 2.4 % on the 40-site J1-J2 Gamma sector with real
@@ -498,6 +514,7 @@ __device__ __forceinline__ int resolve_slot(const DevBasis &db, ulonglong2 q, ui
                                             double2 v_home = make_double2(0.0, 0.0))
 {
     const uint64_t smask = (1ull << db.slot_log2) - 1ull;
+    const uint64_t home_sl = sl;
     bool home = true;
     while (true) {
         if (q.x == kEmpty) return 0;
@@ -514,7 +531,7 @@ __device__ __forceinline__ int resolve_slot(const DevBasis &db, ulonglong2 q, ui
             return 1;
         }
         home = false;
-        sl = (sl + 1) & smask;
+        sl = next_slot(sl, home_sl, smask, CPLX ? 2 : 3);
         q = load_slot<CPLX>(db.slots, sl);
     }
 }

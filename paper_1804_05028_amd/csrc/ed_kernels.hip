@@ -269,6 +269,7 @@ __device__ __forceinline__ int resolve_adj(const DevBasis &db, const char *adj, 
     typedef unsigned long long u64x4 __attribute__((ext_vector_type(4)));
     typedef double f64x2 __attribute__((ext_vector_type(2)));
     const uint64_t smask = (1ull << db.slot_log2) - 1ull;
+    const uint64_t home = sl;
     while (true) {
         if (CPLX) {
             const char *p = adj + (sl << 6);   // {key, -, x.re, x.im, gy.re, gy.im, -, -}
@@ -292,7 +293,7 @@ __device__ __forceinline__ int resolve_adj(const DevBasis &db, const char *adj, 
                 return 1;
             }
         }
-        sl = (sl + 1) & smask;
+        sl = next_slot(sl, home, smask, CPLX ? 2 : 3);   // the H.v slots' sequence
     }
 }
 
@@ -655,7 +656,9 @@ __global__ void k_slots_insert(const uint64_t *states, int64_t D, char *slots, i
     const uint64_t smask = (1ull << log2n) - 1ull;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < D; j += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t key = states[j];
-        uint64_t sl = slot_of_state(key & kStateMask, log2n);
+        const uint64_t home = slot_of_state(key & kStateMask, log2n);
+        const int glog2 = slot_bytes == 32 ? 2 : 3;   // slots per 128-byte line
+        uint64_t sl = home;
         bool done = false;
         for (uint64_t probe = 0; probe <= smask; ++probe) {
             unsigned long long *kp = (unsigned long long *)(slots + sl * (uint64_t)slot_bytes);
@@ -665,7 +668,7 @@ __global__ void k_slots_insert(const uint64_t *states, int64_t D, char *slots, i
                 done = true;
                 break;
             }
-            sl = (sl + 1) & smask;
+            sl = next_slot(sl, home, smask, glog2);
         }
         if (!done) atomicAdd(overflow, 1u);
     }
@@ -1222,7 +1225,7 @@ static int build_impl(ed_basis *b, hipStream_t st)
         const int slot_bytes = dm.is_complex ? 32 : 16;
         const int pct = b->tuning.hash_load_pct > 0 ? std::min(std::max(b->tuning.hash_load_pct, 10), 90) : 30;
         const double need = std::max(2.0, (double)D * 100.0 / pct);
-        const int lg = std::max((int)std::ceil(std::log2(need)), 1);
+        const int lg = std::max((int)std::ceil(std::log2(need)), 4);   // whole lines of slots
         if (lg > 32) return set_error(ED_ERR_UNSUPPORTED, "slot table exceeds 32-bit slot indices");
         b->db.slot_log2 = lg;
         b->n_slots = (int64_t)1 << lg;

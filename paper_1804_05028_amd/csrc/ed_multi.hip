@@ -209,11 +209,12 @@ __global__ void __launch_bounds__((multi_block_bound<KB, SPLIT>()))
         for (int term = 0; term < n_terms; ++term) {
             const uint64_t r = r_nx;
             uint64_t sl = sl_nx;
+            const uint64_t sl_home = sl_nx;
             const uint32_t g = g_nx;
             const double jh = jh_nx;
             ulonglong2 q = q_nx;
             while (q.x != kEmpty && (q.x & kStateMask) != r) {
-                sl = (sl + 1) & smask;
+                sl = next_slot(sl, sl_home, smask, 3);
                 q = load_slot<false>(db.slots, sl);
             }
             const bool found = q.x != kEmpty;
