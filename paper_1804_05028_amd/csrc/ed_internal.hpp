@@ -99,7 +99,7 @@ struct DevBasis {
     int key_bits;              // q
     int key_shift;             // N - m - q
     // hash-slot index: 16-byte (real) or 32-byte (complex) slots
-    // {packed state, amplitude}; open addressing with linear probing
+    // {packed state, amplitude}; open addressing, line-local probe sequence
     char *slots;
     int slot_log2;             // number of slots = 2^slot_log2
     const uint32_t *slot_of;   // [dim] slot index of every representative

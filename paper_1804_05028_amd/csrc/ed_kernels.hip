@@ -4,7 +4,7 @@
 // Data layout in HBM
 //   states[D]   uint64: bits [0,56) representative, bits [56,64) index of its
 //               stabiliser size among the divisors of |G|.
-//   slots       hash-slot index (default): open addressing with linear probing
+//   slots       hash-slot index (default): open addressing, line-local probing
 //               over 16-byte slots {packed state, x} (complex: 32-byte slots
 //               {packed state, -, re, im}) at a low load factor; the input
 //               vector is scattered into the slots before each H.v, so that one
@@ -643,7 +643,7 @@ __global__ void k_limits(const uint64_t *states, int64_t D, const uint16_t *top_
     }
 }
 
-// slot table: clear, then insert every representative by linear probing
+// slot table: clear, then insert every representative along its probe sequence
 __global__ void k_slots_clear(uint64_t *slots_u64, uint64_t n_u64)
 {
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_u64; k += (uint64_t)gridDim.x * blockDim.x)
