@@ -126,6 +126,42 @@ def test_every_wave_of_a_block_with_one_byte_single_chunk_tables(threads, search
         b.close()
 
 
+@pytest.mark.parametrize("threads", [512, 1024])
+@pytest.mark.parametrize("case", ["square16_k3", "square16_k5_u8", "sq16T_k1_fermions"])
+def test_every_wave_of_a_block_complex_and_fermionic(threads, case):
+    """The same for complex sectors (32-byte slots, two loads per slot) with 2-
+    and 1-byte tables, and for a fermionic complex momentum sector (2-byte
+    fermionic entries): every row of 8 and 16 waves per block, three launches,
+    against the oracle."""
+    ed = _ed()
+    x = None
+    if case.endswith("fermions"):
+        c = lat.square((4, 0), (0, 4), rotations=False, mirrors=False, superlattice=wl.SQ_2X2, name="sq16T_4sub")
+        w = wl.FermionWorkload("sq16T_k1", c, lat.characters(c, 1), 7, np.full(c.n_bonds, 1.0), np.full(c.n_bonds, 0.4))
+        m = bf.FermionModel(c.n_sites, c.perm, w.chi, c.bonds, w.t, w.V)
+        st, stab = bf.fbasis(m, w.n_part)
+        x = vec.normal_vector(len(st), seed=9, complex_=True)
+        y_ref, _, _ = bf.fapply(m, st, stab, x)
+        b = ed.FermionBasis.from_workload(w, {"block_threads": threads})
+        run = lambda xd: b.apply(w.t, xd, V=w.V)
+    else:
+        w = wl.square_4x4(momentum_index=3 if case == "square16_k3" else 5)
+        m = bf.Model.from_workload(w)
+        st, stab = bf.basis(m, w.n_up)
+        x = vec.normal_vector(len(st), seed=9, complex_=True)
+        y_ref, _, _ = bf.apply(m, st, stab, x)
+        b = ed.Basis.from_workload(w, {"block_threads": threads, **({"table_entry_bytes": 1} if case.endswith("u8") else {})})
+        run = lambda xd: b.apply(w.J, xd)
+    try:
+        assert b.is_complex and b.dim > 256
+        xd = torch.as_tensor(x).cuda()
+        for _ in range(3):
+            y = run(xd).cpu().numpy()
+            assert np.abs(y - y_ref).max() <= RTOL * np.abs(y_ref).max()
+    finally:
+        b.close()
+
+
 @pytest.mark.parametrize("name", [n for n, _ in SMALL])
 def test_basis_bit_exact(built, name):
     w, b = built[name]
