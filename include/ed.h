@@ -113,11 +113,12 @@ typedef struct {
                                sublattices, else ED_ERR_UNSUPPORTED); 0 = two-stage when a host
                                sample of the search averages at least 3 candidates               */
     int32_t lanes_per_row;  /* batched H.v (ed_build_multi): 1, 2 or 4 lanes share a row, each
-                               running the row's searches and holding every lanes-th sector; 0 = 1 lane for K <= 2, 2 lanes for K <= 8, else 4.
-                               When |G| K 16 bytes of characters exceed 32 KB they are read from
-                               HBM, and the lane count is raised to at least 2 for K > 4 and 4
-                               for K > 16, and K > 32 always runs 4 lanes (ed_multi_info reports the
-                               count used)                                                          */
+                               running the row's searches and holding every lanes-th sector; 0 = 1 lane
+                               for K <= 2, 2 lanes for K <= 8, else 4.  When |G| K 16 bytes of
+                               characters exceed 32 KB they are read from HBM (or, for K <= 8 and
+                               characters all +-1, staged as sign bits): then 0 = 1 lane for K <= 8,
+                               and the count is raised to at least 2 for K > 8 and 4 for K > 16;
+                               K > 32 always runs 4 lanes (ed_multi_info reports the count used)  */
     int32_t lanczos_direct; /* ed_lanczos: 1 = launch each step's kernels directly; 0 = capture the
                                step once per buffer assignment in a HIP graph and replay it        */
 } ed_tuning_t;
@@ -396,6 +397,9 @@ typedef struct {
     int32_t lanes_per_row;      /* lanes per row of the batched H.v kernel     */
     int32_t chi_in_lds;         /* 1: the character table is staged in LDS (counted in lds_bytes);
                                    0: the kernel reads it from HBM through the caches            */
+    int32_t chi_signs;          /* 1: every character is +1 or -1 (real one-dimensional irreps)
+                                   and the table is too large for LDS: the kernel stages one sign
+                                   bit per sector and element instead (|G| bytes, in lds_bytes) */
 } ed_multi_info_t;
 
 #define ED_LANCZOS_NO_GRAPH 1   /* ed_lanczos_batched: launch the step kernels directly */

@@ -78,7 +78,7 @@ class ed_multi_info_t(ctypes.Structure):
                 ("n_bonds", ctypes.c_int32), ("chunk_bits", ctypes.c_int32),
                 ("table_entry_bytes", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("n_slots", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
-                ("lanes_per_row", ctypes.c_int32), ("chi_in_lds", ctypes.c_int32)]
+                ("lanes_per_row", ctypes.c_int32), ("chi_in_lds", ctypes.c_int32), ("chi_signs", ctypes.c_int32)]
 
 
 ED_LANCZOS_NO_GRAPH = 1

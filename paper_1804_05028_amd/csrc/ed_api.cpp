@@ -515,7 +515,19 @@ int ed_build_multi(const ed_lattice_t *lat, const ed_group_t *grp, int32_t n_sec
         return set_error(ED_ERR_UNSUPPORTED, "more than 32 sectors need their character table (%zu bytes) in LDS",
                          chi_bytes);
     }
-    const uint32_t reserve = mb->chi_in_lds ? (uint32_t)((chi_bytes + 15) & ~(size_t)15) : 0u;
+    // a table too large for LDS whose characters are all +1 or -1 (the real
+    // one-dimensional irreps) is staged as one sign bit per sector instead
+    if (!mb->chi_in_lds && n_sectors <= 8) {
+        bool signs = true;
+        for (int k = 0; k < n_sectors && signs; ++k)
+            for (int g = 0; g < ng && signs; ++g) {
+                const double re = irreps[k].chi[2 * g], im = irreps[k].chi[2 * g + 1];
+                signs = (re == 1.0 || re == -1.0) && im == 0.0;
+            }
+        mb->chi_signs = signs;
+    }
+    const uint32_t reserve = mb->chi_in_lds ? (uint32_t)((chi_bytes + 15) & ~(size_t)15)
+                                            : (mb->chi_signs ? (uint32_t)((ng + 15) & ~15) : 0u);
     rc = build_basis_common(lat, grp, &trivial, n_up, &tn, reserve, stream, &mb->base);
     if (rc) {
         delete mb;
@@ -557,8 +569,10 @@ int ed_multi_info(const ed_multi_t *mb, ed_multi_info_t *info)
     info->n_bonds = b->t.nb;
     info->chunk_bits = b->dm.chunk_bits;
     info->table_entry_bytes = b->dm.act_bytes;
-    info->lds_bytes = (int32_t)(mb->lds_chi_off + (mb->chi_in_lds ? (uint32_t)b->t.ng * mb->K * 16 : 0u));
+    info->lds_bytes = (int32_t)(mb->lds_chi_off + (mb->chi_in_lds ? (uint32_t)b->t.ng * mb->K * 16
+                                                                   : (mb->chi_signs ? ((uint32_t)b->t.ng + 15u) & ~15u : 0u)));
     info->chi_in_lds = mb->chi_in_lds ? 1 : 0;
+    info->chi_signs = mb->chi_signs ? 1 : 0;
     info->n_slots = b->n_slots;
     info->device_bytes = b->device_bytes;
     info->build_ms = mb->build_ms;

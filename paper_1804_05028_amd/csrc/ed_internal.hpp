@@ -159,6 +159,8 @@ struct ed_multi {
     std::vector<int64_t> dims;     // [K]
     uint32_t lds_chi_off = 0;      // LDS byte offset of the staged character table
     bool chi_in_lds = true;        // else the kernel reads chi_dev through the caches
+    bool chi_signs = false;        // all characters +-1, table not in LDS: stage sign bits
+    void *sgn_dev = nullptr;       // [ng] bytes (padded to 16): bit k set iff chi_k(g) = -1
     double build_ms = 0.0;
     int grid_blocks = 0;
     // Lanczos workspace, kept between calls

@@ -28,8 +28,10 @@ struct MultiDev {
     int K;
     const uint64_t *masks;    // [dim]
     const double2 *chi;       // [ng][K] in HBM
+    const void *lds_src;      // what is staged at chi_off: chi, or the sign bytes
     uint32_t chi_off;         // LDS byte offset of the staged copy
     uint32_t chi_bytes;       // bytes staged in LDS (0: read chi from HBM)
+    int chi_signs;            // staged: [ng] bytes, bit k set iff chi_k(g) = -1
 };
 
 // per-sector Lanczos state
@@ -141,7 +143,7 @@ __global__ void __launch_bounds__((multi_block_bound<KB, SPLIT>()))
     extern __shared__ __align__(16) char lds[];
     const Ctx<AT> c = stage<AT>(dm, lds);
     double2 *chik = (double2 *)(lds + md.chi_off);
-    lds_copy((char *)chik, md.chi, md.chi_bytes);
+    lds_copy((char *)chik, md.lds_src, md.chi_bytes);
     __syncthreads();
     const int K = md.K;
     const int nb = dm.nb;
@@ -266,9 +268,37 @@ __global__ void __launch_bounds__((multi_block_bound<KB, SPLIT>()))
                     }
                 }
             };
-            // characters chi_k(g) of this lane's sectors: the LDS copy, or
-            // HBM in the instances with registers for a second accumulate path
-            if (kChiHbm && md.chi_bytes == 0)
+            // characters +-1: (ar, ai) += (+-amp) x, the value the complex
+            // product gives for chi = (+-1, 0)
+            auto accumulate_signs = [&](uint32_t sg) {
+                if (kPre) {
+#pragma unroll
+                    for (int k = 0; k < (kPre ? KB : 1); ++k) {
+                        if (k < KL) {
+                            const double a = ((sg >> (koff + SPLIT * k)) & 1u) ? -amp : amp;
+                            ar[k] = fma(a, xv[k].x, ar[k]);
+                            ai[k] = fma(a, xv[k].y, ai[k]);
+                        }
+                    }
+                } else {
+                    const double2 *xj = x + (size_t)(q.y & 0xFFFFFFFFull) * K + koff;
+#pragma unroll
+                    for (int k = 0; k < KB; ++k) {
+                        if (k < KL && ((mij >> (koff + SPLIT * k)) & 1ull)) {
+                            const double a = ((sg >> (koff + SPLIT * k)) & 1u) ? -amp : amp;
+                            const double2 xx = xj[SPLIT * k];
+                            ar[k] = fma(a, xx.x, ar[k]);
+                            ai[k] = fma(a, xx.y, ai[k]);
+                        }
+                    }
+                }
+            };
+            // characters chi_k(g) of this lane's sectors: the LDS copy, their
+            // sign bits in LDS, or HBM; the last two in the instances with
+            // registers for a second accumulate path
+            if (kChiHbm && md.chi_signs)
+                accumulate_signs(((const uint8_t *)chik)[g]);
+            else if (kChiHbm && md.chi_bytes == 0)
                 accumulate(md.chi + (size_t)g * K + koff);
             else
                 accumulate(chik + (size_t)g * K + koff);
@@ -519,7 +549,10 @@ static int multi_launch_impl(const ed_multi *mb, const void *x, void *y, const v
     md.masks = mb->masks;
     md.chi = (const double2 *)mb->chi_dev;
     md.chi_off = mb->lds_chi_off;
-    md.chi_bytes = mb->chi_in_lds ? (uint32_t)((size_t)b->t.ng * mb->K * 16) : 0u;
+    md.chi_bytes = mb->chi_in_lds ? (uint32_t)((size_t)b->t.ng * mb->K * 16)
+                                  : (mb->chi_signs ? ((uint32_t)b->t.ng + 15u) & ~15u : 0u);
+    md.chi_signs = mb->chi_signs ? 1 : 0;
+    md.lds_src = mb->chi_signs ? mb->sgn_dev : mb->chi_dev;
     const size_t lds = (size_t)md.chi_off + md.chi_bytes;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess || per_cu < 1)
@@ -654,6 +687,18 @@ int multi_setup(ed_multi *mb, void *stream)
     HIP_TRY(hipMemsetAsync(d_cnt, 0, (size_t)K * 8, st));
     mb->chi_dev = d_chi;
     mb->masks = (uint64_t *)d_masks;
+    if (mb->chi_signs) {
+        // one byte per element: bit k set iff chi_k(g) = -1 (every character is +-1)
+        std::vector<uint8_t> sgn(((size_t)ng + 15) & ~(size_t)15, 0);
+        for (int g = 0; g < ng; ++g)
+            for (int k = 0; k < K; ++k)
+                if (chi[((size_t)g * K + k) * 2] < 0.0) sgn[g] |= (uint8_t)(1u << k);
+        void *d_sgn = nullptr;
+        rc = device_alloc(b, &d_sgn, sgn.size());
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(d_sgn, sgn.data(), sgn.size(), hipMemcpyHostToDevice, st));
+        mb->sgn_dev = d_sgn;
+    }
     mb->lds_chi_off = (b->dm.lds_total + 15u) & ~15u;
     const uint64_t all = K == 64 ? ~0ull : ((1ull << K) - 1ull);
     if (D > 0) {

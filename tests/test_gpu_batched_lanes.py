@@ -137,6 +137,8 @@ def test_benchmark_instances_match_oracle(name, make, tune, chunks, chi_lds, lan
         info = mb.info()
         assert info["n_sublat"] == 4 and info["table_entry_bytes"] == 2
         assert info["lanes_per_row"] == lanes and info["chi_in_lds"] == int(chi_lds)
+        # the 8 Gamma irreps have characters +-1: above 32 KB, one sign bit each
+        assert info["chi_signs"] == int(not chi_lds)
         m_bits = ws[0].cluster.n_sites // 4
         assert -(-m_bits // info["chunk_bits"]) == chunks
         x = _x(mb.dim, mb.K, 61)

@@ -259,7 +259,24 @@ BATCHED = [
     ("triangular36_gamma_2lanes", lambda: wl.triangular_36_gamma(n_sub=4), {"lanes_per_row": 2}, 2, 2000),
     # the first sixteen momentum sectors, as the all-momentum benchmark groups them
     ("triangular36_allk16", lambda: wl.triangular_36_all_momenta(n_sub=4)[:16], None, 4, 1500),
+    # eight Gamma irreps of 36 T x C6 x flip (no mirrors): complex characters
+    # (sixth roots of unity), 55 KB of them, read from HBM as complex numbers
+    ("triangular36_c6_gamma_complex", lambda: _tri36_c6_gamma()[:8], None, 1, 1500),
 ]
+
+
+def _tri36_c6_gamma():
+    c = lat.triangular((6, 0), (0, 6), spin_flip=True, mirrors=False, superlattice=wl.TRI_4, name="triangular36_c6")
+    return wl.gamma_irreps(wl.Workload("triangular36_c6", c, lat.characters(c, 0), 18, np.ones(c.n_bonds)))
+
+
+def _expected_chi_placement(ws):
+    """(chi_in_lds, chi_signs) as the library chooses them: the table in LDS up
+    to 32 KB; above, sign bits when every character is +-1 and K <= 8."""
+    chis = np.array([w.chi for w in ws])
+    in_lds = chis.size * 16 <= 32768
+    signs = (not in_lds) and len(ws) <= 8 and bool(np.all(np.isin(chis.real, (1.0, -1.0)) & (chis.imag == 0.0)))
+    return int(in_lds), int(signs)
 
 
 @pytest.mark.parametrize("name,make,tuning,lanes,n_rows", BATCHED, ids=[c[0] for c in BATCHED])
@@ -274,6 +291,8 @@ def test_fullsize_batched_sampled_rows(name, make, tuning, lanes, n_rows):
     try:
         info = mb.info()
         assert info["lanes_per_row"] == lanes and info["n_sublat"] == 4
+        assert (info["chi_in_lds"], info["chi_signs"]) == _expected_chi_placement(ws)
+        print(f"[fullsize] {name}: chi_in_lds={info['chi_in_lds']} chi_signs={info['chi_signs']}", flush=True)
         dims = mb.sector_dims()
         for k, w in enumerate(ws):
             c = w.cluster
