@@ -413,7 +413,8 @@ def bench_gamma_batched(reps):
                                                               "Gamma, Sz=0", "n_sectors": len(ws),
             "per_sector_ms": per, "per_sector_total_ms": per_ms, "batched_ms": bat_ms, "speedup": per_ms / bat_ms,
             "terms_per_hv": int(t.sum()), "shared_terms_per_hv": int(shared), "lanes_per_row": info["lanes_per_row"],
-            "chi_in_lds": info["chi_in_lds"], "timing": f"torch.cuda events on the launch stream, mean of {reps}"}
+            "chi_in_lds": info["chi_in_lds"], "chi_signs": info["chi_signs"],
+            "timing": f"torch.cuda events on the launch stream, mean of {reps}"}
 
 
 def wl_mod():
