@@ -46,13 +46,13 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_05028_amd", "csrc", f)
 MEASURED_TRAFFIC = {
     # (workload, n_sublat, index, chunk_bits): (kernel sha256, fetch bytes, write bytes, profile)
     ("square40_j1j2", 4, "hash-slot", 5): (
-        "04bddd1e9146d96fe55c7b60b05d75348846dde83d248b04389f842c8c770666", 4.69342e+12, 3.44728e+09,
+        "7d93300f210f425807423f443e910cb74fc6d5d46019fbbda22fa907fb9a8675", 4.69342e+12, 3.44728e+09,
         "profiles/k_apply_square40_j1j2_ns4.md"),
     ("triangular36_k1", 4, "hash-slot", 5): (
-        "04bddd1e9146d96fe55c7b60b05d75348846dde83d248b04389f842c8c770666", 1.92584e+12, 4.03337e+09,
+        "7d93300f210f425807423f443e910cb74fc6d5d46019fbbda22fa907fb9a8675", 1.92584e+12, 4.03337e+09,
         "profiles/k_apply_triangular36_k1_complex.md"),
     ("triangular36_tV", 4, "hash-slot", 5): (
-        "04bddd1e9146d96fe55c7b60b05d75348846dde83d248b04389f842c8c770666", 3.03372e+11, 3.36083e+08,
+        "7d93300f210f425807423f443e910cb74fc6d5d46019fbbda22fa907fb9a8675", 3.03372e+11, 3.36083e+08,
         "profiles/k_apply_fermions_triangular36_tV.md"),
 }
 
