@@ -46,13 +46,13 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_05028_amd", "csrc", f)
 MEASURED_TRAFFIC = {
     # (workload, n_sublat, index, chunk_bits): (kernel sha256, fetch bytes, write bytes, profile)
     ("square40_j1j2", 4, "hash-slot", 5): (
-        "7d93300f210f425807423f443e910cb74fc6d5d46019fbbda22fa907fb9a8675", 4.69342e+12, 3.44728e+09,
+        "65f865045fddf0948f6d1fd330e70d6f17e56c8eb5eeaf09e04b20826133bfd4", 4.69342e+12, 3.44728e+09,
         "profiles/k_apply_square40_j1j2_ns4.md"),
     ("triangular36_k1", 4, "hash-slot", 5): (
-        "7d93300f210f425807423f443e910cb74fc6d5d46019fbbda22fa907fb9a8675", 1.92584e+12, 4.03337e+09,
+        "65f865045fddf0948f6d1fd330e70d6f17e56c8eb5eeaf09e04b20826133bfd4", 1.92584e+12, 4.03337e+09,
         "profiles/k_apply_triangular36_k1_complex.md"),
     ("triangular36_tV", 4, "hash-slot", 5): (
-        "7d93300f210f425807423f443e910cb74fc6d5d46019fbbda22fa907fb9a8675", 3.03372e+11, 3.36083e+08,
+        "65f865045fddf0948f6d1fd330e70d6f17e56c8eb5eeaf09e04b20826133bfd4", 3.03372e+11, 3.36083e+08,
         "profiles/k_apply_fermions_triangular36_tV.md"),
 }
 

@@ -57,6 +57,13 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
         const uint64_t e = row_ok ? db.states[i] : 0ull;
         const uint64_t s = e & kStateMask;
         const double rs_i = c.div_rsqrt[e >> kNormShift];
+        // Lanczos step: the row's own v_i and v_prev,i requested before the
+        // term loop (in the plain H.v, loading x_i there measured slower)
+        typename Scalar<CPLX>::T xi_pf{}, vp_pf{};
+        if (MODE == 2 && row_ok) {
+            xi_pf = x[i];
+            vp_pf = vprev[i];
+        }
         double anti_sum = 0.0, ar = 0.0, ai = 0.0;
         // antiparallel bonds of this row
         BondMask am;
@@ -171,22 +178,22 @@ __global__ void __launch_bounds__(1024) k_apply(DevModel dm, DevBasis db, const 
         if (MODE == 1 || !row_ok) continue;
         const double d = FERMI ? fdiag : jsum_quarter - anti_sum;
         if (CPLX) {
-            const double2 xi = *(const double2 *)&x[i];
+            const double2 xi = MODE == 2 ? *(const double2 *)&xi_pf : *(const double2 *)&x[i];
             double2 out;
             out.x = d * xi.x + ar;
             out.y = d * xi.y + ai;
             if (MODE == 2) {
-                const double2 vp = *(const double2 *)&vprev[i];
+                const double2 vp = *(const double2 *)&vp_pf;
                 out.x -= beta_prev * vp.x;
                 out.y -= beta_prev * vp.y;
                 acc_part += xi.x * out.x + xi.y * out.y;   // Re(conj(v) w)
             }
             *(double2 *)&y[i] = out;
         } else {
-            const double xi = *(const double *)&x[i];
+            const double xi = MODE == 2 ? *(const double *)&xi_pf : *(const double *)&x[i];
             double out = d * xi + ar;
             if (MODE == 2) {
-                out -= beta_prev * *(const double *)&vprev[i];
+                out -= beta_prev * *(const double *)&vp_pf;
                 acc_part += xi * out;
             }
             *(double *)&y[i] = out;

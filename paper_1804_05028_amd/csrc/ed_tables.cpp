@@ -242,10 +242,15 @@ int build_tables(const ed_lattice_t *lat, const ed_group_t *grp, Tables &t)
     t.sym_off.assign((size_t)ns * (P + 1), 0);
     t.sym_list.clear();
     t.max_sym = 0;
+    // blocks that no element maps onto block 0 (e.g. the spin species of a
+    // Hubbard model as two orbitals per site) can never hold the top block:
+    // their Rep_X is "infinite", stored as 0xFFFF with an empty Sym list
+    std::vector<char> no_top(ns, 0);
     for (int X = 0; X < ns; ++X) {
         std::vector<int> GX;
         for (int g = 0; g < ng; ++g)
             if (t.u_tgt[(size_t)t.g_u[g] * ns + X] == 0) GX.push_back(g);
+        no_top[X] = GX.empty();
         for (uint32_t s = 0; s < P; ++s) {
             uint32_t best = 0xFFFFFFFFu;
             for (int g : GX) {
@@ -274,6 +279,10 @@ int build_tables(const ed_lattice_t *lat, const ed_group_t *grp, Tables &t)
     for (size_t r = 0; r < t.top_vals.size(); ++r) rank[t.top_vals[r]] = (int32_t)r;
     t.rep.resize((size_t)ns * P);
     for (size_t k = 0; k < repv.size(); ++k) {
+        if (no_top[k / P]) {
+            t.rep[k] = 0xFFFFu;
+            continue;
+        }
         int32_t r = rank[repv[k]];
         if (r < 0) return set_error(ED_ERR_NOT_SUBLATTICE_STABLE, "internal: Rep_X value is not a block-0 representative");
         t.rep[k] = ((uint32_t)r << 16) | repv[k];

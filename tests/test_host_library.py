@@ -113,6 +113,39 @@ def test_tables_two_sublattice_example():
         L.ed_tables_free(h)
 
 
+def test_tables_block_that_never_reaches_the_top():
+    """Two orbitals per site as two blocks (the Hubbard ring): no element maps
+    the second block onto the first, so its Rep_X is "infinite" (0xFFFF, no
+    Sym entries) and every representative comes from block 0.  Built many
+    times in one process, since a wrong table index here reads past an
+    array and fails only now and then."""
+    from ed_inputs import workloads as wl
+    w = wl.hubbard_ring(4, 1.0, 2.5, momentum_index=0, n_sub=2)
+    c = w.cluster
+    arrays = L.ModelArrays(c.n_sites, c.bonds, c.n_sublat, c.perm, np.zeros(c.perm.shape[0], np.uint8), None)
+    m = c.n_sites // c.n_sublat
+    for _ in range(50):
+        h = L.ed_tables_create(arrays)
+        try:
+            for sub in range(1 << m):
+                rep1, sym1 = L.ed_tables_sublattice(h, 1, sub)
+                assert rep1 == 0xFFFF and sym1 == []
+            states = np.array([0b10010110, 0b01101001, 0b00111100], np.uint64)
+            r, g, nc = L.ed_tables_find_rep(h, states)
+            for s0, r0, g0 in zip(states.tolist(), r.tolist(), g.tolist()):
+                # the representative is the smallest translate: both species shift together
+                imgs = []
+                for row in c.perm:
+                    v = 0
+                    for i in range(c.n_sites):
+                        if (s0 >> (c.n_sites - 1 - i)) & 1:
+                            v |= 1 << (c.n_sites - 1 - int(row[i]))
+                    imgs.append(v)
+                assert r0 == min(imgs)
+        finally:
+            L.ed_tables_free(h)
+
+
 def test_tables_three_sublattice_example():
     ex = _gold()["three_sublattice"]
     c = lat.chain(6, superlattice_period=3)
