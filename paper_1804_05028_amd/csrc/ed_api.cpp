@@ -171,15 +171,16 @@ static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, co
             delete b;
             return set_error(ED_ERR_UNSUPPORTED, "fermionic bases use the hash-slot index and 2- or 4-byte table entries");
         }
-        if (eb == 2 && (b->t.m > 12 || b->t.ns > 8)) {
+        const int m = b->t.m, ns = b->t.ns;   // read before any delete of b
+        if (eb == 2 && (m > 12 || ns > 8)) {
             delete b;
             return set_error(ED_ERR_UNSUPPORTED,
                              "2-byte fermionic table entries need blocks of at most 12 orbitals and at most 8 "
-                             "sublattices (%d, %d)", b->t.m, b->t.ns);
+                             "sublattices (%d, %d)", m, ns);
         }
-        if (b->t.m > 16) {
+        if (m > 16) {
             delete b;
-            return set_error(ED_ERR_UNSUPPORTED, "fermionic blocks hold at most 16 orbitals (%d)", b->t.m);
+            return set_error(ED_ERR_UNSUPPORTED, "fermionic blocks hold at most 16 orbitals (%d)", m);
         }
         b->fermion = 1;
     }
@@ -210,8 +211,9 @@ static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, co
     }
     b->divs = ed::divisors_of((uint32_t)t.ng);
     if (b->divs.size() > 255) {
+        const int ng = t.ng;   // t lives in *b
         delete b;
-        return set_error(ED_ERR_UNSUPPORTED, "|G|=%d has more than 255 divisors", t.ng);
+        return set_error(ED_ERR_UNSUPPORTED, "|G|=%d has more than 255 divisors", ng);
     }
     ed::DevModel &dm = b->dm;
     dm.N = t.N;
@@ -228,8 +230,9 @@ static int build_basis_common(const ed_lattice_t *lat, const ed_group_t *grp, co
     b->mean_candidates = sample_mean_candidates(t, n_up);
     const bool two_stage_ok = t.ns >= 2 && t.ns <= 4;
     if (b->tuning.search_mode == ED_SEARCH_TWO_STAGE && !two_stage_ok) {
+        const int ns = t.ns;   // t lives in *b
         delete b;
-        return set_error(ED_ERR_UNSUPPORTED, "the two-stage search needs 2 to 4 sublattices (%d)", t.ns);
+        return set_error(ED_ERR_UNSUPPORTED, "the two-stage search needs 2 to 4 sublattices (%d)", ns);
     }
     b->staged = two_stage_ok && (b->tuning.search_mode == ED_SEARCH_TWO_STAGE ||
                                  (b->tuning.search_mode == 0 && b->mean_candidates >= kTwoStageMinCandidates));
